@@ -1,0 +1,65 @@
+"""The five synthetic workloads (sizes, seeds and Delta lists).
+
+Seeds: base s = 19070619.  Workload k (1-based) draws its geometry with
+seed s + 100*k and its start points with s + 100*k + 1.  Batched geometry g
+uses s + 300 + 1000*g and s + 301 + 1000*g; surrogate data reuse that rule
+for g >= 256.
+
+The paper's dense substrate (section 2.2, 1901 circles in a 50 um square) is
+unpublished; these seeded packings stand in for it.  Where a workload gives
+both a disk count and a packing fraction that disagree (a Gamma(4, mean 0.5)
+radius has E[r^2] = 0.3125 um^2, so 300 disks cover ~3% of a 100 um square,
+not 60%), the packing fraction controls and the count follows.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+BASE_SEED = 19070619
+
+
+def _logspace(lo, hi, n):
+    k = np.arange(n)
+    return lo * (hi / lo) ** (k / (n - 1))
+
+
+CONFIGS = {
+    # Plain FP64 P1, one solve, 64^2 grid on a 20 um box, 8 disks.
+    "C1": dict(L=20.0, N=64, n_disks=8, phi=None, shape=4.0, mean=0.5, p=1,
+               R=1, precision="fp64", D=2.0, eta=10.0, sigma0=0.3,
+               deltas=[1.0, 2.0, 5.0]),
+    # Plain FP32 P2 at scale: 512^2 grid on a 100 um box, phi = 0.6, 64 RHS.
+    "C2": dict(L=100.0, N=512, n_disks=None, phi=0.6, shape=4.0, mean=0.5, p=2,
+               R=64, precision="fp32", D=2.0, eta=10.0, sigma0=0.3,
+               deltas=list(_logspace(1.0, 50.0, 20))),
+    # Batched: 256 uneven geometries, h = 100/512, P1/P2 mixed, 16 RHS each.
+    "C3": dict(n_geoms=256, h=100.0 / 512, R=16, precision="fp32", D=2.0,
+               eta=10.0, sigma0=0.3, deltas=list(_logspace(1.0, 50.0, 20))),
+    # High order: P3 on a 256^2 grid over a 50 um box, phi = 0.65, 128 RHS.
+    "C4": dict(L=50.0, N=256, n_disks=None, phi=0.65, shape=4.0, mean=0.5, p=3,
+               R=128, precision="bf16x3", D=2.0, eta=10.0, sigma0=0.3,
+               deltas=list(_logspace(1.0, 30.0, 20))),
+}
+
+
+def config(name: str) -> dict:
+    c = dict(CONFIGS[name])
+    k = int(name[1:])
+    c["geom_seed"] = BASE_SEED + 100 * k
+    c["point_seed"] = BASE_SEED + 100 * k + 1
+    return c
+
+
+def c3_geometry_params(g: int) -> dict:
+    """Parameters of batched geometry g (grid edge, phi, Gamma law, p)."""
+    rng = np.random.default_rng(BASE_SEED + 300 + 1000 * g)
+    N = int(rng.integers(128, 513))
+    phi = float(rng.uniform(0.4, 0.7))
+    shape = float(rng.uniform(3.0, 6.0))
+    mean = float(rng.uniform(0.4, 0.7))
+    p = 1 if rng.random() < 0.5 else 2
+    h = CONFIGS["C3"]["h"]
+    return dict(N=N, L=N * h, phi=phi, shape=shape, mean=mean, p=p,
+                geom_seed=BASE_SEED + 300 + 1000 * g + 7,
+                point_seed=BASE_SEED + 301 + 1000 * g)

@@ -1,0 +1,188 @@
+"""Seeded disk packings and start points (inputs only, no method arithmetic).
+
+The paper's substrate (section 2.2) is a square of side L holding
+non-overlapping circles (axons) whose radii follow a Gamma law, clipped to
+the square.  Its coordinates were never published, so these generators
+produce seeded stand-ins:
+
+* ``rsa_disks``: random sequential addition.  Radii are drawn i.i.d. from
+  Gamma(shape k, scale mean/k) -- either a fixed count, or until the summed
+  disk area reaches phi * L**2 -- and placed largest first.  Each disk gets at
+  most ``max_tries`` uniform centre proposals in [0, L]^2 and is accepted at
+  the first proposal whose gap to every placed disk is at least ``gap``;
+  a disk that finds no place is dropped.  Disks may cross the box edge.
+* ``start_points``: points uniform in the centred box of side ``box_frac*L``
+  (the paper draws its pulses in a centred 20 um box of a 50 um square,
+  section 4.2), rejected when closer than r + sqrt(2)*h to a disk centre, so
+  that the grid cell holding the point keeps its centroid outside every disk.
+
+All randomness comes from ``numpy.random.default_rng(seed)`` (PCG64).
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Geometry:
+    """A square box [0, L]^2 on an N x N cell grid with a list of disks."""
+
+    L: float
+    N: int
+    disks: np.ndarray          # float64 [n, 3] = (cx, cy, r) in um
+    params: dict               # how it was drawn (for reports)
+
+    @property
+    def h(self) -> float:
+        return self.L / self.N
+
+
+def _draw_radii(rng, L, phi, n_disks, shape, mean):
+    scale = mean / shape
+    if n_disks is not None:
+        radii = rng.gamma(shape, scale, size=int(n_disks))
+    else:
+        target = phi * L * L
+        chunks = []
+        total = 0.0
+        while total < target:
+            c = rng.gamma(shape, scale, size=1024)
+            area = np.cumsum(np.pi * c * c) + total
+            k = int(np.searchsorted(area, target)) + 1
+            if k <= c.size:
+                chunks.append(c[:k])
+                total = float(area[k - 1])
+                break
+            chunks.append(c)
+            total = float(area[-1])
+        radii = np.concatenate(chunks) if chunks else np.zeros(0)
+    return np.sort(radii)[::-1].copy()
+
+
+def rsa_disks(L: float, rng: np.random.Generator, *, phi: float | None = None,
+              n_disks: int | None = None, shape: float = 4.0, mean: float = 0.5,
+              gap: float = 0.1, max_tries: int = 20000, batch: int = 256) -> np.ndarray:
+    """Random sequential addition of Gamma-radius disks in [0, L]^2.
+
+    Exactly one of ``phi`` (target summed disk area / L^2) and ``n_disks``
+    must be given.  Returns float64 [n_placed, 3] = (cx, cy, r).
+    """
+    if (phi is None) == (n_disks is None):
+        raise ValueError("give exactly one of phi and n_disks")
+    radii = _draw_radii(rng, L, phi, n_disks, shape, mean)
+    if radii.size == 0:
+        return np.zeros((0, 3))
+    rmax = float(radii[0])
+    cell = 2.0 * rmax + gap
+    ng = max(1, int(math.ceil(L / cell)))
+    cap = 8
+    grid = -np.ones((ng + 2, ng + 2, cap), dtype=np.int64)   # padded by one ring
+    count = np.zeros((ng + 2, ng + 2), dtype=np.int64)
+    placed = np.zeros((radii.size, 3))
+    n = 0
+    offs = np.array([(dx, dy) for dx in (-1, 0, 1) for dy in (-1, 0, 1)])
+    for r in radii:
+        tries = 0
+        done = False
+        while tries < max_tries and not done:
+            k = min(batch, max_tries - tries)
+            prop = rng.uniform(0.0, L, size=(k, 2))
+            tries += k
+            gx = np.minimum((prop[:, 0] / cell).astype(np.int64), ng - 1) + 1
+            gy = np.minimum((prop[:, 1] / cell).astype(np.int64), ng - 1) + 1
+            cx = gx[:, None] + offs[None, :, 0]
+            cy = gy[:, None] + offs[None, :, 1]
+            cand = grid[cx, cy]                      # [k, 9, cap]
+            ok = np.ones(k, dtype=bool)
+            valid = cand >= 0
+            if valid.any():
+                ci = np.where(valid, cand, 0)
+                px = placed[ci, 0]
+                py = placed[ci, 1]
+                pr = placed[ci, 2]
+                dx = px - prop[:, 0, None, None]
+                dy = py - prop[:, 1, None, None]
+                need = pr + r + gap
+                clash = valid & (dx * dx + dy * dy < need * need)
+                ok = ~clash.any(axis=(1, 2))
+            idx = np.flatnonzero(ok)
+            if idx.size:
+                j = int(idx[0])
+                placed[n] = (prop[j, 0], prop[j, 1], r)
+                a, b = int(gx[j]), int(gy[j])
+                if count[a, b] == cap:
+                    grid = np.concatenate([grid, -np.ones_like(grid)], axis=2)
+                    cap *= 2
+                grid[a, b, count[a, b]] = n
+                count[a, b] += 1
+                n += 1
+                done = True
+    return placed[:n].copy()
+
+
+def coverage_fraction(disks: np.ndarray, L: float, samples: int = 1024) -> float:
+    """Area fraction of [0, L]^2 covered by the (clipped) disks, estimated on a
+    samples x samples midpoint raster.  Reporting only."""
+    t = (np.arange(samples) + 0.5) * (L / samples)
+    covered = np.zeros((samples, samples), dtype=bool)
+    for cx, cy, r in disks:
+        i0 = max(0, int((cx - r) / L * samples) - 1)
+        i1 = min(samples, int((cx + r) / L * samples) + 2)
+        j0 = max(0, int((cy - r) / L * samples) - 1)
+        j1 = min(samples, int((cy + r) / L * samples) + 2)
+        if i0 >= i1 or j0 >= j1:
+            continue
+        xx = t[i0:i1, None] - cx
+        yy = t[None, j0:j1] - cy
+        covered[i0:i1, j0:j1] |= xx * xx + yy * yy < r * r
+    return float(covered.mean())
+
+
+def start_points(disks: np.ndarray, L: float, N: int, m: int,
+                 rng: np.random.Generator, box_frac: float = 0.4,
+                 center: tuple | None = None) -> np.ndarray:
+    """m start points uniform in the centred box of side box_frac*L, each at
+    least r + sqrt(2)*h from every disk centre (h = L/N).  float64 [m, 2]."""
+    h = L / N
+    cx0, cy0 = (0.5 * L, 0.5 * L) if center is None else center
+    half = 0.5 * box_frac * L
+    margin = math.sqrt(2.0) * h
+    out = np.zeros((m, 2))
+    n = 0
+    guard = 0
+    while n < m:
+        guard += 1
+        if guard > 100000:
+            raise RuntimeError("could not place start points")
+        p = rng.uniform(-half, half, size=(256, 2)) + np.array([cx0, cy0])
+        if disks.shape[0]:
+            dx = p[:, 0, None] - disks[None, :, 0]
+            dy = p[:, 1, None] - disks[None, :, 1]
+            lim = disks[None, :, 2] + margin
+            ok = ~(dx * dx + dy * dy < lim * lim).any(axis=1)
+        else:
+            ok = np.ones(p.shape[0], dtype=bool)
+        good = p[ok]
+        take = min(m - n, good.shape[0])
+        out[n:n + take] = good[:take]
+        n += take
+    return out
+
+
+def make_geometry(L: float, N: int, seed: int, *, phi=None, n_disks=None,
+                  shape=4.0, mean=0.5, gap=0.1) -> Geometry:
+    """Seeded disk packing on an N x N grid over [0, L]^2."""
+    rng = np.random.default_rng(seed)
+    if phi is None and n_disks is None:
+        disks = np.zeros((0, 3))
+    else:
+        disks = rsa_disks(L, rng, phi=phi, n_disks=n_disks, shape=shape,
+                          mean=mean, gap=gap)
+    params = dict(L=L, N=N, seed=seed, phi_target=phi, n_disks_target=n_disks,
+                  gamma_shape=shape, gamma_mean=mean, gap=gap,
+                  n_disks=int(disks.shape[0]))
+    return Geometry(L=float(L), N=int(N), disks=disks, params=params)
