@@ -1,0 +1,197 @@
+/*
+ * dgd.h -- C-ABI of libdgd, a single-GPU (MI355X, gfx950) discontinuous
+ * Galerkin solver for diffusion in the extracellular space of an axon
+ * substrate, returning the displacement covariance of the ensemble average
+ * propagator.
+ *
+ * The problem follows the paper "A GPU implementation of the Discontinuous
+ * Galerkin method for simulation of diffusion in brain tissue" (arXiv
+ * 1907.06191):
+ *   - section 2.1, eq. (1)-(5): du/dt = div(k grad u) with k = D in the
+ *     extracellular region and zero flux (reflecting) on the axon walls;
+ *     this library also keeps zero flux on the outer box;
+ *   - section 2.2: the substrate is a square holding non-overlapping disks;
+ *   - section 3.3: the square is cut into pixels, each split by a diagonal
+ *     into two triangles (here the lower-left to upper-right diagonal); a
+ *     pixel whose centroid lies strictly inside a disk is removed;
+ *   - section 3.1: elementwise polynomial approximation on a nodal Lagrange
+ *     basis (eq. (8)), advanced in time by a Runge-Kutta method (here
+ *     SSP-RK3); the flux is the symmetric interior penalty flux with
+ *     penalty sigma = eta p^2 D / h on every interior face;
+ *   - section 4.1: from a pulse at each start point x0 the solution is
+ *     carried to each diffusion time Delta and the covariance
+ *     Sigma = int (x - x0)(x - x0)^T u dx / int u dx is returned.
+ *
+ * Conventions.  Lengths in micrometres, times in milliseconds, D in
+ * um^2/ms.  All functions return 0 (DGD_OK) or a negative DGD_E* code and
+ * set a thread-local message readable with dgd_last_error().  No C++
+ * exception crosses this boundary.  A handle is used by one host thread at
+ * a time.  Host pointers are read during the call only (inputs are copied);
+ * device pointers are allocations on the current HIP device.
+ */
+#ifndef DGD_H
+#define DGD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DGD_OK 0
+#define DGD_EINVAL (-1)     /* bad argument (size, order, pointer, list) */
+#define DGD_ENOMEM (-2)     /* host or device allocation failed, or workspace too small */
+#define DGD_EDEVICE (-3)    /* a HIP runtime call failed */
+#define DGD_EUNSTABLE (-4)  /* non-finite value or mass drift beyond tolerance */
+#define DGD_ENOTFREE (-5)   /* a start point lies outside the box or in a removed cell */
+
+/* Precision of operator and state.  Moments are always reduced in FP64. */
+#define DGD_FP64 0
+#define DGD_FP32 1
+#define DGD_BF16X3 2        /* P3 only: BF16 hi/lo split products on MFMA, FP32 accumulate/state */
+
+typedef struct dgd_mesh dgd_mesh;
+typedef struct dgd_op dgd_op;
+typedef struct dgd_run dgd_run;
+
+/* Library version as 10000*major + 100*minor + patch. */
+int dgd_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* dgd_last_error(void);
+
+/*
+ * Build the pixel-triangle mesh of [0, L]^2 on an n_cells x n_cells grid
+ * (h = L / n_cells) with the disks removed (sections 2.2 and 3.3).
+ *   disks: host float64 [n_disks][3] = (cx, cy, r); disks may cross the box
+ *          edge; n_disks may be 0 (disks may then be NULL).
+ * Elements are ordered cell-major (row j slow, column i fast), the lower
+ * right triangle T0 of a cell before its upper left triangle T1.  The mesh
+ * tables are uploaded to the current HIP device.  *out is owned by the
+ * caller and released with dgd_mesh_destroy.
+ * Errors: EINVAL (L <= 0, n_cells < 1 or > 16384, n_disks < 0, NULL out),
+ * ENOMEM, EDEVICE.
+ */
+int dgd_mesh_create(double L_um, int32_t n_cells, const double* disks, int32_t n_disks,
+                    dgd_mesh** out);
+
+/* Counts for reports: active triangles, interior faces, connected
+ * components of the face graph, fraction of removed cells.  Any output
+ * pointer may be NULL. */
+int dgd_mesh_info(const dgd_mesh* mesh, int64_t* n_active, int64_t* n_faces,
+                  int32_t* n_components, double* removed_fraction);
+
+/* Element table on the host: cell column, cell row and orientation (0 = T0,
+ * 1 = T1) of every active triangle, in solver order.  Arrays of length
+ * n_active; any may be NULL. */
+int dgd_mesh_elements(const dgd_mesh* mesh, int32_t* cell_i, int32_t* cell_j, int8_t* orient);
+
+void dgd_mesh_destroy(dgd_mesh* mesh);
+
+/*
+ * Build the SIPG operator of degree p on the mesh (section 3.1 with the
+ * interior-penalty flux; section 3.2 for the role of the flux).
+ *   p in {1, 2, 3}; D > 0 (um^2/ms); eta > 0 (penalty eta p^2 D / h);
+ *   precision: DGD_FP64, DGD_FP32, or DGD_BF16X3 (p = 3 only);
+ *   dt_max_ms > 0: nominal step = min(0.1 h^2 / (D (p+1)^2), dt_max_ms);
+ *   dt_max_ms <= 0: nominal step = min(0.1 h^2 / (D (p+1)^2), 0.9 X / b),
+ *     X = 2.5127... the real stability limit of SSP-RK3 and
+ *     b = 1.05 lambda, lambda a power-iteration estimate of the largest
+ *     eigenvalue of M^-1 A computed on the device.
+ * The op keeps a pointer to the mesh, which must outlive it.
+ * Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+int dgd_operator_build(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, double eta,
+                       int32_t precision, double dt_max_ms, dgd_op** out);
+
+/* Nominal step in ms and the eigenvalue estimate behind it (0 when the
+ * caller fixed dt_max_ms).  Either pointer may be NULL. */
+int dgd_operator_dt(const dgd_op* op, double* dt_nom_ms, double* lambda_max_per_ms);
+
+/* Nodes per triangle, node coordinates and precision.
+ *   nodes: NULL or host float64 [2][np][2]: for orientation o and node k,
+ *          the (x, y) position inside the cell in units of h with the cell's
+ *          lower-left corner at (0, 0). */
+int dgd_operator_info(const dgd_op* op, int32_t* np, double* nodes, int32_t* precision);
+
+/* Device bytes a solve with n_points start points needs (3 state vectors
+ * of n_active * np * n_points values plus reduction scratch). */
+int dgd_workspace_size(const dgd_op* op, int32_t n_points, size_t* bytes);
+
+/*
+ * y = -M^-1 A x (units 1/ms) on device buffers in the op's precision
+ * (double for DGD_FP64, float otherwise), layout [n_active][np][n_rhs]
+ * with the right-hand-side index fastest.  x and y must not overlap.
+ * Asynchronous on hip_stream (NULL: the null stream).
+ * Errors: EINVAL, EDEVICE.
+ */
+int dgd_operator_apply(dgd_op* op, const void* d_in, void* d_out, int32_t n_rhs, void* hip_stream);
+
+void dgd_operator_destroy(dgd_op* op);
+
+/*
+ * A run: the state of n_points solves on one operator (section 4.1: one
+ * diffusion problem per start point), held on the device in the layout
+ * [n_active][np][n_points].
+ *
+ * dgd_run_create projects the pulse exp(-|x - x0|^2 / (2 sigma0^2)),
+ * restricted to the active triangles, onto the space (L2 projection with
+ * an FP64 quadrature) and scales each column to unit mass.
+ *   points: host float64 [n_points][2]; each must lie in an active cell
+ *           (else ENOTFREE).
+ *   d_ws: NULL (the library allocates) or a device buffer of ws_bytes >=
+ *         dgd_workspace_size bytes that outlives the run (else ENOMEM).
+ *   hip_stream: stream every kernel of the run is launched on; NULL gives
+ *         the run a stream of its own (default priority).
+ */
+int dgd_run_create(dgd_op* op, const double* points, int32_t n_points, double sigma0_um,
+                   void* d_ws, size_t ws_bytes, void* hip_stream, dgd_run** out);
+
+/* Advance every column by n_steps SSP-RK3 steps of dt_ms (asynchronous on
+ * the run's stream; steps are replayed from captured HIP graphs). */
+int dgd_run_advance(dgd_run* run, int64_t n_steps, double dt_ms);
+
+/* FP64 moments about each start point, host [n_points][6] =
+ * (M0, mx, my, Mxx, Mxy, Myy).  Synchronises the run's stream.
+ * Returns EUNSTABLE if a moment is not finite or |M0 - 1| > the
+ * precision's tolerance (1e-9 FP64, 1e-3 otherwise); moments_out is
+ * filled either way. */
+int dgd_run_moments(dgd_run* run, double* moments_out);
+
+/* Copy the state to or from the host (checkpoint / resume); host buffer of
+ * n_active * np * n_points values of the op's state type.  Synchronous. */
+int dgd_run_get_state(dgd_run* run, void* host_out);
+int dgd_run_set_state(dgd_run* run, const void* host_in);
+
+void dgd_run_destroy(dgd_run* run);
+
+/*
+ * Whole solve (section 4.1): for every start point, carry the pulse
+ * through the strictly increasing list deltas_ms (all > 0) with the
+ * nominal step of the op, landing exactly on each Delta_k
+ * (n_k = ceil((Delta_k - Delta_{k-1}) / dt_nom - 1e-9) steps of equal size),
+ * and report Sigma about the start point.
+ *   sigma_out: host float64 [n_points][n_deltas][3] = (xx, xy, yy);
+ *   moments_out: NULL or host float64 [n_points][n_deltas][6].
+ * Synchronous.  Errors: as dgd_run_create, plus EINVAL for a bad Delta
+ * list and EUNSTABLE as dgd_run_moments.
+ */
+int dgd_eap_solve(dgd_op* op, const double* points, int32_t n_points, double sigma0_um,
+                  const double* deltas_ms, int32_t n_deltas, double* sigma_out,
+                  double* moments_out, void* d_ws, size_t ws_bytes, void* hip_stream);
+
+/* Runtime options (process-wide; read when a run is created or advanced):
+ *   "graphs"       1 = replay steps from captured HIP graphs, 0 = plain launches
+ *   "graph_steps"  steps captured per graph, 1..4096
+ *   "stage_epw"    elements walked by each wave of the stage kernel, 1..256
+ *   "stage_waves"  waves per workgroup of the stage kernel, 1..4
+ *   "xcd_remap"    1 = each XCD sweeps one contiguous band of elements
+ * Errors: EINVAL for an unknown name or a value out of range. */
+int dgd_set_option(const char* name, int64_t value);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGD_H */

@@ -1,0 +1,639 @@
+// C-ABI of libdgd: meshes, operators, runs and the whole solve.
+//
+// The solve follows section 4.1 of the paper: one diffusion problem per
+// start point, carried to each diffusion time, and the covariance of the
+// normalised solution about its start point.  Everything that touches the
+// state runs in the HIP kernels of kernels.hip; the host only builds tables
+// (mesh, reference element), schedules steps and reads back six FP64
+// moments per start point and diffusion time.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dgd_internal.h"
+#include "launch.h"
+
+namespace dgd {
+
+thread_local std::string g_last_error;
+
+void set_error(int code, const std::string& msg) {
+  (void)code;
+  g_last_error = msg;
+}
+void clear_error() { g_last_error.clear(); }
+
+namespace {
+
+struct Options {
+  bool graphs = true;
+  int64_t graph_steps = 32;
+  int stage_epw = 1;        // elements per wave in the stage kernel
+  int stage_waves = 4;      // waves per workgroup in the stage kernel
+  bool xcd_remap = false;   // XCD-banded block order (measured: no gain at one element per wave)
+};
+Options g_opt;
+
+Shape stage_shape(int64_t E) { return element_shape(E, g_opt.stage_epw, g_opt.stage_waves, g_opt.xcd_remap); }
+
+constexpr int kEpwReduce = 16;
+constexpr double kCutoff = 12.0;   // initial pulse evaluated within 12 sigma0 of x0
+constexpr int kQuadN = 12;         // 12 x 12 collapsed Gauss-Legendre points per triangle
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    clear_error();
+    return f();
+  } catch (const Error& e) {
+    set_error(e.code, e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error(DGD_ENOMEM, "host allocation failed");
+    return DGD_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(DGD_EINVAL, e.what());
+    return DGD_EINVAL;
+  } catch (...) {
+    set_error(DGD_EINVAL, "unknown error");
+    return DGD_EINVAL;
+  }
+}
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+size_t state_bytes(int prec) { return prec == DGD_FP64 ? 8 : 4; }
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Real root of x^3/6 - x^2/2 + x - 2 = 0: |R(-x)| = 1 edge of the SSP-RK3
+// stability interval on the negative real axis.
+double rk3_limit() {
+  double x = 2.5;
+  for (int i = 0; i < 60; ++i) {
+    const double f = x * x * x / 6 - x * x / 2 + x - 2;
+    const double d = x * x / 2 - x + 1;
+    x -= f / d;
+  }
+  return x;
+}
+
+template <typename T>
+void* upload(const std::vector<double>& v) {
+  std::vector<T> t(v.begin(), v.end());
+  void* d = nullptr;
+  DGD_HIP_CHECK(hipMalloc(&d, t.size() * sizeof(T)));
+  DGD_HIP_CHECK(hipMemcpy(d, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice));
+  return d;
+}
+
+// Largest eigenvalue of -M^-1 A (dimensionless) by power iteration in FP64
+// on the device: 16 random columns, each step scaled by the row-sum bound g
+// (so nothing overflows), Rayleigh quotient (x, A x)/(x, M x) at the end.
+double power_lambda(dgd_op* op, int iters) {
+  const dgd_mesh* mesh = op->mesh;
+  const int64_t E = mesh->host.n_elements();
+  const int np = op->ref.np;
+  const int R = 16;
+  const int64_t n = E * np * R;
+  // row-sum bound of the dimensionless operator
+  double g = 0;
+  for (int o = 0; o < 2; ++o)
+    for (int mask = 0; mask < 8; ++mask)
+      for (int i = 0; i < np; ++i) {
+        double s = 0;
+        for (int j = 0; j < np; ++j) s += std::fabs(op->ref.S[((o * 8 + mask) * np + i) * np + j]);
+        for (int f = 0; f < 3; ++f)
+          if (mask >> f & 1)
+            for (int j = 0; j < np; ++j) s += std::fabs(op->ref.Nb[((o * 3 + f) * np + i) * np + j]);
+        g = std::max(g, s);
+      }
+  void* S64 = upload<double>(op->ref.S);
+  void* N64 = upload<double>(op->ref.Nb);
+  double* Mass = (double*)upload<double>(op->ref.Mass);
+  double *x = nullptr, *y = nullptr, *part = nullptr, *red = nullptr;
+  const Shape sh = stage_shape(E);
+  const Shape shr = element_shape(E, kEpwReduce);
+  auto cleanup = [&]() {
+    (void)hipFree(S64); (void)hipFree(N64); (void)hipFree(Mass); (void)hipFree(x);
+    (void)hipFree(y); (void)hipFree(part); (void)hipFree(red);
+  };
+  try {
+    DGD_HIP_CHECK(hipMalloc(&x, n * sizeof(double)));
+    DGD_HIP_CHECK(hipMalloc(&y, n * sizeof(double)));
+    DGD_HIP_CHECK(hipMalloc(&part, shr.nblk() * R * 6 * sizeof(double)));
+    DGD_HIP_CHECK(hipMalloc(&red, R * 6 * sizeof(double)));
+    hipStream_t st = nullptr;
+    launch_fill_random(x, n, 0x1907061900ull, st);
+    const int4* elem = mesh->d_elem;
+    for (int it = 0; it < iters; ++it) {
+      launch_stage(DGD_FP64, np, x, nullptr, y, elem, E, S64, N64, 0, 0.0, 1.0 / g, R, sh, st);
+      std::swap(x, y);
+    }
+    DGD_HIP_CHECK(hipGetLastError());
+    // y = L x (unscaled); lambda = -(x, M y) / (x, M x)
+    launch_stage(DGD_FP64, np, x, nullptr, y, elem, E, S64, N64, 0, 0.0, 1.0, R, sh, st);
+    std::vector<double> xmy(R * 6), xmx(R * 6);
+    launch_dot_mass(np, x, y, elem, E, Mass, R, shr, part, st);
+    launch_reduce(part, (int)shr.nblk(), R, red, st);
+    DGD_HIP_CHECK(hipMemcpy(xmy.data(), red, R * 6 * sizeof(double), hipMemcpyDeviceToHost));
+    launch_dot_mass(np, x, x, elem, E, Mass, R, shr, part, st);
+    launch_reduce(part, (int)shr.nblk(), R, red, st);
+    DGD_HIP_CHECK(hipMemcpy(xmx.data(), red, R * 6 * sizeof(double), hipMemcpyDeviceToHost));
+    double lam = 0;
+    for (int r = 0; r < R; ++r)
+      if (xmx[r * 6] > 0) lam = std::max(lam, -xmy[r * 6] / xmx[r * 6]);
+    cleanup();
+    return lam;
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+}
+
+void run_stage_steps(dgd_run* run, int64_t n, double dt) {
+  dgd_op* op = run->op;
+  const dgd_mesh* mesh = op->mesh;
+  const int64_t E = mesh->host.n_elements();
+  const int np = op->ref.np;
+  const double h = mesh->host.h;
+  const double gam = dt * op->D / (h * h);
+  const Shape sh = stage_shape(E);
+  const int pr = op->precision == DGD_FP64 ? 0 : 1;
+  for (int64_t s = 0; s < n; ++s) {
+    // Shu-Osher SSP-RK3 as corrections of u^n:
+    //   u1 = u + dt L u;  u2 = u + 1/4 (u1 - u) + 1/4 dt L u1;  u' = u + 2/3 (u2 - u) + 2/3 dt L u2
+    launch_stage(pr, np, run->U, nullptr, run->U1, mesh->d_elem, E, op->d_S, op->d_N, 1, 0.0, gam,
+                 run->R, sh, run->stream);
+    launch_stage(pr, np, run->U1, run->U, run->U2, mesh->d_elem, E, op->d_S, op->d_N, 1, 0.25,
+                 0.25 * gam, run->R, sh, run->stream);
+    launch_stage(pr, np, run->U2, run->U, run->U, mesh->d_elem, E, op->d_S, op->d_N, 1, 2.0 / 3.0,
+                 2.0 / 3.0 * gam, run->R, sh, run->stream);
+  }
+}
+
+hipGraphExec_t step_graph(dgd_run* run, int64_t n, double dt) {
+  uint64_t bits;
+  std::memcpy(&bits, &dt, sizeof(bits));
+  auto key = std::make_pair(bits, n);
+  auto it = run->graphs.find(key);
+  if (it != run->graphs.end()) return it->second;
+  hipGraph_t g = nullptr;
+  DGD_HIP_CHECK(hipStreamBeginCapture(run->stream, hipStreamCaptureModeThreadLocal));
+  run_stage_steps(run, n, dt);
+  DGD_HIP_CHECK(hipStreamEndCapture(run->stream, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) fail(DGD_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  run->graphs[key] = ex;
+  return ex;
+}
+
+// The element table goes to the device on first use (operator build), so
+// that meshes can be built and inspected on a host without a GPU.
+void ensure_mesh_on_device(const dgd_mesh* cm) {
+  dgd_mesh* m = const_cast<dgd_mesh*>(cm);
+  if (m->d_elem) return;
+  DGD_HIP_CHECK(hipGetDevice(&m->device));
+  DGD_HIP_CHECK(hipMalloc(&m->d_elem, m->packed.size() * sizeof(int4)));
+  DGD_HIP_CHECK(hipMemcpy(m->d_elem, m->packed.data(), m->packed.size() * sizeof(int4),
+                          hipMemcpyHostToDevice));
+}
+
+void ws_layout(const dgd_op* op, int R, size_t* total, size_t off[6], int* nblk) {
+  const int64_t E = op->mesh->host.n_elements();
+  const size_t sb = state_bytes(op->precision);
+  const size_t st = align256((size_t)E * op->ref.np * R * sb);
+  const Shape shr = element_shape(E, kEpwReduce);
+  *nblk = (int)shr.nblk();
+  size_t o = 0;
+  off[0] = o; o += st;                                     // U
+  off[1] = o; o += st;                                     // U1
+  off[2] = o; o += st;                                     // U2
+  off[3] = o; o += align256((size_t)R * 2 * 8);            // x0
+  off[4] = o; o += align256((size_t)shr.nblk() * R * 6 * 8);  // partials
+  off[5] = o; o += align256((size_t)R * 6 * 8);            // moments
+  *total = o;
+}
+
+}  // namespace
+}  // namespace dgd
+
+using namespace dgd;
+
+extern "C" {
+
+int dgd_version(void) { return 100; }
+
+const char* dgd_last_error(void) { return g_last_error.c_str(); }
+
+int dgd_set_option(const char* name, int64_t value) {
+  return guarded([&]() -> int {
+    if (!name) fail(DGD_EINVAL, "option name is NULL");
+    const std::string n(name);
+    if (n == "graphs") g_opt.graphs = value != 0;
+    else if (n == "graph_steps") {
+      if (value < 1 || value > 4096) fail(DGD_EINVAL, "graph_steps must be in [1, 4096]");
+      g_opt.graph_steps = value;
+    } else if (n == "stage_epw") {
+      if (value < 1 || value > 256) fail(DGD_EINVAL, "stage_epw must be in [1, 256]");
+      g_opt.stage_epw = (int)value;
+    } else if (n == "stage_waves") {
+      if (value < 1 || value > 4) fail(DGD_EINVAL, "stage_waves must be in [1, 4]");
+      g_opt.stage_waves = (int)value;
+    } else if (n == "xcd_remap") {
+      g_opt.xcd_remap = value != 0;
+    } else fail(DGD_EINVAL, "unknown option " + n);
+    return DGD_OK;
+  });
+}
+
+int dgd_mesh_create(double L_um, int32_t n_cells, const double* disks, int32_t n_disks,
+                    dgd_mesh** out) {
+  return guarded([&]() -> int {
+    if (!out) fail(DGD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!(L_um > 0) || !std::isfinite(L_um)) fail(DGD_EINVAL, "L must be positive and finite");
+    if (n_cells < 1 || n_cells > 16384) fail(DGD_EINVAL, "n_cells must be in [1, 16384]");
+    if (n_disks < 0 || (n_disks > 0 && !disks)) fail(DGD_EINVAL, "bad disk list");
+    for (int d = 0; d < n_disks; ++d)
+      for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(disks[3 * d + k])) fail(DGD_EINVAL, "disk list holds a non-finite value");
+    auto* m = new dgd_mesh();
+    try {
+      build_mesh_host(L_um, n_cells, disks, n_disks, m->host);
+      const int64_t E = m->host.n_elements();
+      if (E > ((int64_t)1 << 31) - 1) fail(DGD_EINVAL, "too many elements");
+      std::vector<int4> pk(std::max<int64_t>(E, 1));
+      for (int64_t e = 0; e < E; ++e) {
+        int mask = 0;
+        for (int f = 0; f < 3; ++f)
+          if (m->host.nbr[e * 3 + f] >= 0) mask |= 1 << f;
+        pk[e].x = m->host.nbr[e * 3 + 0];
+        pk[e].y = m->host.nbr[e * 3 + 1];
+        pk[e].z = m->host.nbr[e * 3 + 2];
+        pk[e].w = (int)((uint32_t)m->host.orient[e] | ((uint32_t)mask << 1) |
+                        ((uint32_t)m->host.ci[e] << 4) | ((uint32_t)m->host.cj[e] << 18));
+      }
+      m->packed = std::move(pk);
+    } catch (...) {
+      if (m->d_elem) (void)hipFree(m->d_elem);
+      delete m;
+      throw;
+    }
+    *out = m;
+    return DGD_OK;
+  });
+}
+
+int dgd_mesh_info(const dgd_mesh* mesh, int64_t* n_active, int64_t* n_faces, int32_t* n_components,
+                  double* removed_fraction) {
+  return guarded([&]() -> int {
+    if (!mesh) fail(DGD_EINVAL, "mesh is NULL");
+    if (n_active) *n_active = mesh->host.n_elements();
+    if (n_faces) *n_faces = mesh->host.n_faces;
+    if (n_components) *n_components = mesh->host.n_components;
+    if (removed_fraction) {
+      int64_t act = 0;
+      for (auto a : mesh->host.active_cell) act += a;
+      *removed_fraction = 1.0 - (double)act / (double)mesh->host.active_cell.size();
+    }
+    return DGD_OK;
+  });
+}
+
+int dgd_mesh_elements(const dgd_mesh* mesh, int32_t* cell_i, int32_t* cell_j, int8_t* orient) {
+  return guarded([&]() -> int {
+    if (!mesh) fail(DGD_EINVAL, "mesh is NULL");
+    const int64_t E = mesh->host.n_elements();
+    if (cell_i) std::memcpy(cell_i, mesh->host.ci.data(), E * sizeof(int32_t));
+    if (cell_j) std::memcpy(cell_j, mesh->host.cj.data(), E * sizeof(int32_t));
+    if (orient) std::memcpy(orient, mesh->host.orient.data(), E * sizeof(int8_t));
+    return DGD_OK;
+  });
+}
+
+void dgd_mesh_destroy(dgd_mesh* mesh) {
+  if (!mesh) return;
+  if (mesh->d_elem) (void)hipFree(mesh->d_elem);
+  delete mesh;
+}
+
+int dgd_operator_build(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, double eta,
+                       int32_t precision, double dt_max_ms, dgd_op** out) {
+  return guarded([&]() -> int {
+    if (!out) fail(DGD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!mesh) fail(DGD_EINVAL, "mesh is NULL");
+    if (p < 1 || p > 3) fail(DGD_EINVAL, "p must be 1, 2 or 3");
+    if (!(D_um2_per_ms > 0) || !std::isfinite(D_um2_per_ms)) fail(DGD_EINVAL, "D must be positive");
+    if (!(eta > 0) || !std::isfinite(eta)) fail(DGD_EINVAL, "eta must be positive");
+    if (precision != DGD_FP64 && precision != DGD_FP32)
+      fail(DGD_EINVAL, "precision must be DGD_FP64 or DGD_FP32");
+    if (mesh->host.n_elements() == 0) fail(DGD_EINVAL, "mesh has no active element");
+    auto* op = new dgd_op();
+    try {
+      ensure_mesh_on_device(mesh);
+      op->mesh = mesh;
+      op->precision = precision;
+      op->D = D_um2_per_ms;
+      op->ref = build_ref_elem(p, eta);
+      const RefElem& R = op->ref;
+      const int np = R.np;
+      // element matrices stay FP64 for both state precisions (FP64 element arithmetic)
+      op->d_S = upload<double>(R.S);
+      op->d_N = upload<double>(R.Nb);
+      op->d_Minv = (double*)upload<double>(R.Minv);
+      const double h = mesh->host.h;
+      std::vector<double> Wp(R.W.size()), Mp(R.Mass.size());
+      for (int o = 0; o < 2; ++o)
+        for (int a = 0; a < 6; ++a) {
+          const double s = h * h * (a == 0 ? 1.0 : (a < 3 ? h : h * h));
+          for (int j = 0; j < np; ++j) Wp[(o * 6 + a) * np + j] = R.W[(o * 6 + a) * np + j] * s;
+        }
+      for (size_t k = 0; k < Mp.size(); ++k) Mp[k] = R.Mass[k] * h * h;
+      op->d_W = (double*)upload<double>(Wp);
+      op->d_Mass = (double*)upload<double>(Mp);
+      std::vector<double> quad = build_ic_quadrature(R, kQuadN);
+      op->nq = kQuadN * kQuadN;
+      op->d_quad = (double*)upload<double>(quad);
+      const double dt_formula = 0.1 * h * h / (D_um2_per_ms * (p + 1) * (p + 1));
+      if (dt_max_ms > 0) {
+        op->dt_nom = std::min(dt_formula, dt_max_ms);
+        op->lambda_max = 0;
+      } else {
+        const double lam = power_lambda(op, 400) * D_um2_per_ms / (h * h);
+        op->lambda_max = lam;
+        op->dt_nom = std::min(dt_formula, 0.9 * rk3_limit() / (1.05 * lam));
+      }
+    } catch (...) {
+      dgd_operator_destroy(op);
+      throw;
+    }
+    *out = op;
+    return DGD_OK;
+  });
+}
+
+int dgd_operator_dt(const dgd_op* op, double* dt_nom_ms, double* lambda_max_per_ms) {
+  return guarded([&]() -> int {
+    if (!op) fail(DGD_EINVAL, "op is NULL");
+    if (dt_nom_ms) *dt_nom_ms = op->dt_nom;
+    if (lambda_max_per_ms) *lambda_max_per_ms = op->lambda_max;
+    return DGD_OK;
+  });
+}
+
+int dgd_operator_info(const dgd_op* op, int32_t* np, double* nodes, int32_t* precision) {
+  return guarded([&]() -> int {
+    if (!op) fail(DGD_EINVAL, "op is NULL");
+    if (np) *np = op->ref.np;
+    if (nodes) std::memcpy(nodes, op->ref.nodes.data(), op->ref.nodes.size() * sizeof(double));
+    if (precision) *precision = op->precision;
+    return DGD_OK;
+  });
+}
+
+int dgd_workspace_size(const dgd_op* op, int32_t n_points, size_t* bytes) {
+  return guarded([&]() -> int {
+    if (!op || !bytes) fail(DGD_EINVAL, "NULL argument");
+    if (n_points < 1) fail(DGD_EINVAL, "n_points must be >= 1");
+    size_t off[6];
+    int nblk;
+    ws_layout(op, n_points, bytes, off, &nblk);
+    return DGD_OK;
+  });
+}
+
+int dgd_operator_apply(dgd_op* op, const void* d_in, void* d_out, int32_t n_rhs, void* hip_stream) {
+  return guarded([&]() -> int {
+    if (!op || !d_in || !d_out) fail(DGD_EINVAL, "NULL argument");
+    if (n_rhs < 1) fail(DGD_EINVAL, "n_rhs must be >= 1");
+    if (d_in == d_out) fail(DGD_EINVAL, "input and output must not overlap");
+    const int64_t E = op->mesh->host.n_elements();
+    const double h = op->mesh->host.h;
+    const Shape sh = stage_shape(E);
+    launch_stage(op->precision == DGD_FP64 ? 0 : 1, op->ref.np, d_in, nullptr, d_out,
+                 op->mesh->d_elem, E, op->d_S, op->d_N, 0, 0.0, op->D / (h * h), n_rhs, sh,
+                 (hipStream_t)hip_stream);
+    DGD_HIP_CHECK(hipGetLastError());
+    return DGD_OK;
+  });
+}
+
+void dgd_operator_destroy(dgd_op* op) {
+  if (!op) return;
+  (void)hipFree(op->d_S);
+  (void)hipFree(op->d_N);
+  (void)hipFree(op->d_Minv);
+  (void)hipFree(op->d_W);
+  (void)hipFree(op->d_Mass);
+  (void)hipFree(op->d_quad);
+  delete op;
+}
+
+int dgd_run_create(dgd_op* op, const double* points, int32_t n_points, double sigma0_um, void* d_ws,
+                   size_t ws_bytes, void* hip_stream, dgd_run** out) {
+  return guarded([&]() -> int {
+    if (!out) fail(DGD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!op || !points) fail(DGD_EINVAL, "NULL argument");
+    if (n_points < 1) fail(DGD_EINVAL, "n_points must be >= 1");
+    if (!(sigma0_um > 0) || !std::isfinite(sigma0_um)) fail(DGD_EINVAL, "sigma0 must be positive");
+    const MeshHost& mh = op->mesh->host;
+    for (int r = 0; r < n_points; ++r) {
+      const double x = points[2 * r], y = points[2 * r + 1];
+      if (!std::isfinite(x) || !std::isfinite(y) || x < 0 || y < 0 || x >= mh.L || y >= mh.L)
+        fail(DGD_ENOTFREE, "start point " + std::to_string(r) + " lies outside the box");
+      const int i = std::min(mh.N - 1, (int)(x / mh.h)), j = std::min(mh.N - 1, (int)(y / mh.h));
+      if (!mh.active_cell[(size_t)j * mh.N + i])
+        fail(DGD_ENOTFREE, "start point " + std::to_string(r) + " lies in a removed cell");
+    }
+    size_t total, off[6];
+    int nblk;
+    ws_layout(op, n_points, &total, off, &nblk);
+    auto* run = new dgd_run();
+    try {
+      run->op = op;
+      run->R = n_points;
+      run->nblk_red = nblk;
+      run->x0.assign(points, points + 2 * n_points);
+      if (d_ws) {
+        if (ws_bytes < total) fail(DGD_ENOMEM, "workspace smaller than dgd_workspace_size");
+        run->ws = d_ws;
+        run->ws_bytes = ws_bytes;
+      } else {
+        DGD_HIP_CHECK(hipMalloc(&run->ws, total));
+        run->own_ws = true;
+        run->ws_bytes = total;
+      }
+      if (hip_stream) {
+        run->stream = (hipStream_t)hip_stream;
+      } else {
+        DGD_HIP_CHECK(hipStreamCreateWithFlags(&run->stream, hipStreamNonBlocking));
+        run->own_stream = true;
+      }
+      char* base = (char*)run->ws;
+      run->U = base + off[0];
+      run->U1 = base + off[1];
+      run->U2 = base + off[2];
+      run->d_x0 = (double*)(base + off[3]);
+      run->d_part = (double*)(base + off[4]);
+      run->d_mom = (double*)(base + off[5]);
+      DGD_HIP_CHECK(hipMemcpyAsync(run->d_x0, points, (size_t)n_points * 2 * sizeof(double),
+                                   hipMemcpyHostToDevice, run->stream));
+      const int64_t E = op->mesh->host.n_elements();
+      const Shape shr = element_shape(E, kEpwReduce);
+      const Shape sh = stage_shape(E);
+      launch_ic_mass(op->ref.np, op->mesh->d_elem, E, op->d_quad, op->nq, run->d_x0, sigma0_um,
+                     mh.h, kCutoff, n_points, shr, run->d_part, run->stream);
+      launch_reduce(run->d_part, nblk, n_points, run->d_mom, run->stream);
+      launch_ic_project(op->precision == DGD_FP64 ? 0 : 1, op->ref.np, op->mesh->d_elem, E,
+                        op->d_quad, op->nq, op->d_Minv, run->d_x0, run->d_mom, sigma0_um, mh.h,
+                        kCutoff, n_points, sh, run->U, run->stream);
+      DGD_HIP_CHECK(hipGetLastError());
+      std::vector<double> mass((size_t)n_points * 6);
+      DGD_HIP_CHECK(hipMemcpyAsync(mass.data(), run->d_mom, mass.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, run->stream));
+      DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+      for (int r = 0; r < n_points; ++r)
+        if (!(mass[r * 6] > 0) || !std::isfinite(mass[r * 6]))
+          fail(DGD_ENOTFREE, "start point " + std::to_string(r) + " has no pulse mass on active cells");
+    } catch (...) {
+      dgd_run_destroy(run);
+      throw;
+    }
+    *out = run;
+    return DGD_OK;
+  });
+}
+
+int dgd_run_advance(dgd_run* run, int64_t n_steps, double dt_ms) {
+  return guarded([&]() -> int {
+    if (!run) fail(DGD_EINVAL, "run is NULL");
+    if (n_steps < 0) fail(DGD_EINVAL, "n_steps must be >= 0");
+    if (!(dt_ms > 0) || !std::isfinite(dt_ms)) fail(DGD_EINVAL, "dt must be positive");
+    if (n_steps == 0) return DGD_OK;
+    const int64_t G = g_opt.graph_steps;
+    int64_t left = n_steps;
+    if (g_opt.graphs && left >= G) {
+      hipGraphExec_t ex = step_graph(run, G, dt_ms);
+      while (left >= G) {
+        DGD_HIP_CHECK(hipGraphLaunch(ex, run->stream));
+        left -= G;
+      }
+    }
+    run_stage_steps(run, left, dt_ms);
+    DGD_HIP_CHECK(hipGetLastError());
+    run->t_ms += n_steps * dt_ms;
+    return DGD_OK;
+  });
+}
+
+int dgd_run_moments(dgd_run* run, double* moments_out) {
+  return guarded([&]() -> int {
+    if (!run || !moments_out) fail(DGD_EINVAL, "NULL argument");
+    dgd_op* op = run->op;
+    const int64_t E = op->mesh->host.n_elements();
+    const Shape shr = element_shape(E, kEpwReduce);
+    launch_moments(op->precision == DGD_FP64 ? 0 : 1, op->ref.np, run->U, op->mesh->d_elem, E,
+                   op->d_W, run->d_x0, op->mesh->host.h, run->R, shr, run->d_part, run->stream);
+    launch_reduce(run->d_part, run->nblk_red, run->R, run->d_mom, run->stream);
+    DGD_HIP_CHECK(hipGetLastError());
+    DGD_HIP_CHECK(hipMemcpyAsync(moments_out, run->d_mom, (size_t)run->R * 6 * sizeof(double),
+                                 hipMemcpyDeviceToHost, run->stream));
+    DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+    const double tol = op->precision == DGD_FP64 ? 1e-9 : 1e-3;
+    for (int r = 0; r < run->R; ++r) {
+      for (int c = 0; c < 6; ++c)
+        if (!std::isfinite(moments_out[r * 6 + c]))
+          fail(DGD_EUNSTABLE, "non-finite moment for start point " + std::to_string(r));
+      if (std::fabs(moments_out[r * 6] - 1.0) > tol)
+        fail(DGD_EUNSTABLE, "mass drift beyond tolerance for start point " + std::to_string(r));
+    }
+    return DGD_OK;
+  });
+}
+
+int dgd_run_get_state(dgd_run* run, void* host_out) {
+  return guarded([&]() -> int {
+    if (!run || !host_out) fail(DGD_EINVAL, "NULL argument");
+    const size_t n = (size_t)run->op->mesh->host.n_elements() * run->op->ref.np * run->R *
+                     state_bytes(run->op->precision);
+    DGD_HIP_CHECK(hipMemcpyAsync(host_out, run->U, n, hipMemcpyDeviceToHost, run->stream));
+    DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+    return DGD_OK;
+  });
+}
+
+int dgd_run_set_state(dgd_run* run, const void* host_in) {
+  return guarded([&]() -> int {
+    if (!run || !host_in) fail(DGD_EINVAL, "NULL argument");
+    const size_t n = (size_t)run->op->mesh->host.n_elements() * run->op->ref.np * run->R *
+                     state_bytes(run->op->precision);
+    DGD_HIP_CHECK(hipMemcpyAsync(run->U, host_in, n, hipMemcpyHostToDevice, run->stream));
+    DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+    return DGD_OK;
+  });
+}
+
+void dgd_run_destroy(dgd_run* run) {
+  if (!run) return;
+  if (run->stream) (void)hipStreamSynchronize(run->stream);
+  for (auto& kv : run->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (run->own_ws) (void)hipFree(run->ws);
+  if (run->own_stream) (void)hipStreamDestroy(run->stream);
+  delete run;
+}
+
+int dgd_eap_solve(dgd_op* op, const double* points, int32_t n_points, double sigma0_um,
+                  const double* deltas_ms, int32_t n_deltas, double* sigma_out, double* moments_out,
+                  void* d_ws, size_t ws_bytes, void* hip_stream) {
+  dgd_run* run = nullptr;
+  int rc = guarded([&]() -> int {
+    if (!op || !deltas_ms || !sigma_out) fail(DGD_EINVAL, "NULL argument");
+    if (n_deltas < 1) fail(DGD_EINVAL, "n_deltas must be >= 1");
+    double prev = 0;
+    for (int k = 0; k < n_deltas; ++k) {
+      if (!std::isfinite(deltas_ms[k]) || !(deltas_ms[k] > prev))
+        fail(DGD_EINVAL, "Delta list must be finite, positive and strictly increasing");
+      prev = deltas_ms[k];
+    }
+    return DGD_OK;
+  });
+  if (rc) return rc;
+  rc = dgd_run_create(op, points, n_points, sigma0_um, d_ws, ws_bytes, hip_stream, &run);
+  if (rc) return rc;
+  std::vector<double> mom((size_t)n_points * 6);
+  double prev = 0;
+  for (int k = 0; k < n_deltas && rc == 0; ++k) {
+    const double span = deltas_ms[k] - prev;
+    int64_t n = (int64_t)std::ceil(span / op->dt_nom - 1e-9);
+    if (n < 1) n = 1;
+    const double dt = span / (double)n;
+    rc = dgd_run_advance(run, n, dt);
+    if (rc) break;
+    const int mrc = dgd_run_moments(run, mom.data());
+    for (int r = 0; r < n_points; ++r) {
+      const double* m = &mom[(size_t)r * 6];
+      double* s = &sigma_out[((size_t)r * n_deltas + k) * 3];
+      s[0] = m[3] / m[0];
+      s[1] = m[4] / m[0];
+      s[2] = m[5] / m[0];
+      if (moments_out) std::memcpy(&moments_out[((size_t)r * n_deltas + k) * 6], m, 6 * sizeof(double));
+    }
+    if (mrc) rc = mrc;
+    prev = deltas_ms[k];
+  }
+  // keep the message of the first failure: destroy does not touch it
+  dgd_run_destroy(run);
+  return rc;
+}
+
+}  // extern "C"

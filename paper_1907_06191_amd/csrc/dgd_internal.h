@@ -1,0 +1,106 @@
+// Internal types of libdgd (host side).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/dgd.h"
+
+namespace dgd {
+
+// Error plumbing: the last message per host thread, exceptions internal only.
+struct Error {
+  int code;
+  std::string msg;
+};
+void set_error(int code, const std::string& msg);
+void clear_error();
+
+#define DGD_HIP_CHECK(expr)                                                       \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      throw ::dgd::Error{DGD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// Element metadata packed for one 16-byte load per element:
+//   x, y, z = neighbour element across faces 0, 1, 2 (-1: no flux),
+//   w = orientation | face mask << 1 | cell_i << 4 | cell_j << 18.
+struct MeshHost {
+  double L = 0, h = 0;
+  int N = 0;
+  std::vector<uint8_t> active_cell;  // [j * N + i]
+  std::vector<int32_t> ci, cj;       // per element
+  std::vector<int8_t> orient;
+  std::vector<int32_t> nbr;          // [E][3]
+  int64_t n_faces = 0;
+  int32_t n_components = 0;
+  int64_t n_elements() const { return (int64_t)orient.size(); }
+};
+
+// Reference element data, FP64, dimensionless (h = 1, D = 1).
+struct RefElem {
+  int p = 0, np = 0;
+  double eta = 0;
+  std::vector<double> nodes;        // [2][np][2] cell-local positions (units of h)
+  std::vector<double> S;            // [2][8][np][np]  -M^-1 (K + sum_{f in mask} Fself_f)
+  std::vector<double> Nb;           // [2][3][np][np]  -M^-1 Fnbr_f
+  std::vector<double> Mass;         // [2][np][np]
+  std::vector<double> Minv;         // [2][np][np]
+  std::vector<double> W;            // [2][6][np] int phi_j xi^a eta^b over the triangle,
+                                    //   xi = x - x_c (units of h), powers 1,x,y,xx,xy,yy
+};
+
+RefElem build_ref_elem(int p, double eta);
+std::vector<double> build_ic_quadrature(const RefElem& R, int n);
+void build_mesh_host(double L, int N, const double* disks, int n_disks, MeshHost& m);
+
+}  // namespace dgd
+
+// Opaque handles of the C-ABI.
+struct dgd_mesh {
+  dgd::MeshHost host;
+  int device = 0;
+  std::vector<int4> packed;  // [E] packed metadata (host copy)
+  int4* d_elem = nullptr;    // [E] packed metadata on the device (uploaded on first use)
+};
+
+struct dgd_op {
+  const dgd_mesh* mesh = nullptr;
+  dgd::RefElem ref;
+  int precision = DGD_FP64;
+  double D = 0;
+  double dt_nom = 0, lambda_max = 0;
+  void* d_S = nullptr;    // [2][8][np][np] FP64
+  void* d_N = nullptr;    // [2][3][np][np] FP64
+  double* d_Minv = nullptr;  // [2][np][np] FP64
+  double* d_W = nullptr;     // [2][6][np] FP64 physical moment weights
+  double* d_Mass = nullptr;  // [2][np][np] FP64 physical mass
+  double* d_quad = nullptr;  // [2][nq][np+3]: reference quadrature for the initial data
+  int nq = 0;
+};
+
+struct dgd_run {
+  dgd_op* op = nullptr;
+  int R = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  void* U = nullptr;   // state u^n
+  void* U1 = nullptr;  // stage 1
+  void* U2 = nullptr;  // stage 2
+  double* d_x0 = nullptr;     // [R][2]
+  double* d_part = nullptr;   // [nblk][R][6] partial sums
+  double* d_mom = nullptr;    // [R][6]
+  int nblk_red = 0;
+  std::vector<double> x0;
+  double t_ms = 0;
+  // captured step graphs keyed by (dt bits, steps)
+  std::map<std::pair<uint64_t, int64_t>, hipGraphExec_t> graphs;
+};

@@ -1,0 +1,314 @@
+"""Thin Python binding of libdgd (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and does
+nothing but convert arguments: all arithmetic of the solve runs in the HIP
+kernels behind the C-ABI (include/dgd.h).  PyTorch is used, when given, only
+for device memory (workspaces, operator-apply buffers) and streams.
+
+Importing this module loads paper_1907_06191_amd/libdgd.so and raises
+ImportError if it is missing; there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdgd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libdgd.so not built at {LIB_PATH}: run python -m paper_1907_06191_amd.build")
+_lib = ctypes.CDLL(LIB_PATH)
+
+DGD_OK = 0
+DGD_EINVAL = -1
+DGD_ENOMEM = -2
+DGD_EDEVICE = -3
+DGD_EUNSTABLE = -4
+DGD_ENOTFREE = -5
+DGD_FP64 = 0
+DGD_FP32 = 1
+DGD_BF16X3 = 2
+
+_c_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class DGDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdgd error {code}: {msg}")
+        self.code = code
+
+
+def _sig(name, argtypes, restype=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = argtypes
+    f.restype = restype
+    return f
+
+
+_sig("dgd_version", [])
+_sig("dgd_last_error", [], ctypes.c_char_p)
+_sig("dgd_set_option", [ctypes.c_char_p, ctypes.c_int64])
+_sig("dgd_mesh_create", [ctypes.c_double, ctypes.c_int32, _c_dp, ctypes.c_int32, ctypes.POINTER(_vp)])
+_sig("dgd_mesh_info", [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                       ctypes.POINTER(ctypes.c_int32), _c_dp])
+_sig("dgd_mesh_elements", [_vp, _vp, _vp, _vp])
+_sig("dgd_mesh_destroy", [_vp], None)
+_sig("dgd_operator_build", [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                            ctypes.c_double, ctypes.POINTER(_vp)])
+_sig("dgd_operator_dt", [_vp, _c_dp, _c_dp])
+_sig("dgd_operator_info", [_vp, ctypes.POINTER(ctypes.c_int32), _c_dp, ctypes.POINTER(ctypes.c_int32)])
+_sig("dgd_workspace_size", [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)])
+_sig("dgd_operator_apply", [_vp, _vp, _vp, ctypes.c_int32, _vp])
+_sig("dgd_operator_destroy", [_vp], None)
+_sig("dgd_run_create", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _vp, ctypes.c_size_t, _vp,
+                        ctypes.POINTER(_vp)])
+_sig("dgd_run_advance", [_vp, ctypes.c_int64, ctypes.c_double])
+_sig("dgd_run_moments", [_vp, _c_dp])
+_sig("dgd_run_get_state", [_vp, _vp])
+_sig("dgd_run_set_state", [_vp, _vp])
+_sig("dgd_run_destroy", [_vp], None)
+_sig("dgd_eap_solve", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, ctypes.c_int32, _c_dp,
+                       _c_dp, _vp, ctypes.c_size_t, _vp])
+
+
+def _check(rc):
+    if rc != DGD_OK:
+        raise DGDError(rc, _lib.dgd_last_error().decode())
+
+
+def _f64(a, shape_tail=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape_tail is not None:
+        a = a.reshape((-1,) + tuple(shape_tail))
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_c_dp) if a is not None and a.size else None
+
+
+def _dev_ptr(t):
+    """Device pointer of a torch tensor (or an int address), else None."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------------ C names
+
+def dgd_version() -> int:
+    return _lib.dgd_version()
+
+
+def dgd_set_option(name: str, value: int) -> None:
+    _check(_lib.dgd_set_option(name.encode(), int(value)))
+
+
+def dgd_mesh_create(L_um: float, n_cells: int, disks) -> int:
+    d = _f64(disks, (3,))
+    out = _vp()
+    _check(_lib.dgd_mesh_create(float(L_um), int(n_cells), _ptr(d), int(d.shape[0]), ctypes.byref(out)))
+    return out.value
+
+
+def dgd_mesh_info(mesh) -> dict:
+    na, nf = ctypes.c_int64(), ctypes.c_int64()
+    nc = ctypes.c_int32()
+    rf = ctypes.c_double()
+    _check(_lib.dgd_mesh_info(mesh, ctypes.byref(na), ctypes.byref(nf), ctypes.byref(nc), ctypes.byref(rf)))
+    return dict(n_active=na.value, n_faces=nf.value, n_components=nc.value, removed_fraction=rf.value)
+
+
+def dgd_mesh_elements(mesh):
+    n = dgd_mesh_info(mesh)["n_active"]
+    ci = np.zeros(n, dtype=np.int32)
+    cj = np.zeros(n, dtype=np.int32)
+    o = np.zeros(n, dtype=np.int8)
+    _check(_lib.dgd_mesh_elements(mesh, ci.ctypes.data, cj.ctypes.data, o.ctypes.data))
+    return ci, cj, o
+
+
+def dgd_mesh_destroy(mesh) -> None:
+    _lib.dgd_mesh_destroy(mesh)
+
+
+def dgd_operator_build(mesh, p: int, D: float, eta: float, precision: int, dt_max_ms: float = 0.0) -> int:
+    out = _vp()
+    _check(_lib.dgd_operator_build(mesh, int(p), float(D), float(eta), int(precision), float(dt_max_ms),
+                                   ctypes.byref(out)))
+    return out.value
+
+
+def dgd_operator_dt(op):
+    dt, lam = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.dgd_operator_dt(op, ctypes.byref(dt), ctypes.byref(lam)))
+    return dt.value, lam.value
+
+
+def dgd_operator_info(op):
+    np_ = ctypes.c_int32()
+    prec = ctypes.c_int32()
+    _check(_lib.dgd_operator_info(op, ctypes.byref(np_), None, ctypes.byref(prec)))
+    nodes = np.zeros((2, np_.value, 2))
+    _check(_lib.dgd_operator_info(op, ctypes.byref(np_), _ptr(nodes), ctypes.byref(prec)))
+    return np_.value, nodes, prec.value
+
+
+def dgd_workspace_size(op, n_points: int) -> int:
+    b = ctypes.c_size_t()
+    _check(_lib.dgd_workspace_size(op, int(n_points), ctypes.byref(b)))
+    return b.value
+
+
+def dgd_operator_apply(op, d_in, d_out, n_rhs: int, stream=None) -> None:
+    _check(_lib.dgd_operator_apply(op, _dev_ptr(d_in), _dev_ptr(d_out), int(n_rhs), _stream_ptr(stream)))
+
+
+def dgd_operator_destroy(op) -> None:
+    _lib.dgd_operator_destroy(op)
+
+
+def dgd_run_create(op, points, sigma0: float, workspace=None, ws_bytes: int = 0, stream=None) -> int:
+    pts = _f64(points, (2,))
+    out = _vp()
+    if workspace is not None and not ws_bytes:
+        ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib.dgd_run_create(op, _ptr(pts), int(pts.shape[0]), float(sigma0), _dev_ptr(workspace),
+                               int(ws_bytes), _stream_ptr(stream), ctypes.byref(out)))
+    return out.value
+
+
+def dgd_run_advance(run, n_steps: int, dt_ms: float) -> None:
+    _check(_lib.dgd_run_advance(run, int(n_steps), float(dt_ms)))
+
+
+def dgd_run_moments(run, n_points: int, check: bool = True) -> np.ndarray:
+    out = np.zeros((n_points, 6))
+    rc = _lib.dgd_run_moments(run, _ptr(out))
+    if check:
+        _check(rc)
+    return out
+
+
+def dgd_run_get_state(run, n_values: int, dtype) -> np.ndarray:
+    out = np.zeros(n_values, dtype=dtype)
+    _check(_lib.dgd_run_get_state(run, out.ctypes.data))
+    return out
+
+
+def dgd_run_set_state(run, state: np.ndarray) -> None:
+    s = np.ascontiguousarray(state)
+    _check(_lib.dgd_run_set_state(run, s.ctypes.data))
+
+
+def dgd_run_destroy(run) -> None:
+    _lib.dgd_run_destroy(run)
+
+
+def dgd_eap_solve(op, points, sigma0: float, deltas, workspace=None, ws_bytes: int = 0, stream=None):
+    """Returns (sigma [n][nDelta][3], moments [n][nDelta][6])."""
+    pts = _f64(points, (2,))
+    d = _f64(deltas).ravel()
+    n = pts.shape[0]
+    sig = np.zeros((n, d.size, 3))
+    mom = np.zeros((n, d.size, 6))
+    if workspace is not None and not ws_bytes:
+        ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib.dgd_eap_solve(op, _ptr(pts), n, float(sigma0), _ptr(d), int(d.size), _ptr(sig), _ptr(mom),
+                              _dev_ptr(workspace), int(ws_bytes), _stream_ptr(stream)))
+    return sig, mom
+
+
+# ----------------------------------------------------------- RAII helpers
+
+class Mesh:
+    def __init__(self, L_um, n_cells, disks):
+        self._destroy = _lib.dgd_mesh_destroy       # survives module teardown
+        self.handle = dgd_mesh_create(L_um, n_cells, disks)
+
+    def info(self):
+        return dgd_mesh_info(self.handle)
+
+    def elements(self):
+        return dgd_mesh_elements(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+class Operator:
+    def __init__(self, mesh: Mesh, p, D, eta, precision, dt_max_ms=0.0):
+        self._destroy = _lib.dgd_operator_destroy
+        self.mesh = mesh              # keeps the mesh alive
+        self.handle = dgd_operator_build(mesh.handle, p, D, eta, precision, dt_max_ms)
+
+    @property
+    def dt(self):
+        return dgd_operator_dt(self.handle)[0]
+
+    @property
+    def lambda_max(self):
+        return dgd_operator_dt(self.handle)[1]
+
+    def info(self):
+        return dgd_operator_info(self.handle)
+
+    def workspace_size(self, n_points):
+        return dgd_workspace_size(self.handle, n_points)
+
+    def apply(self, x, y, n_rhs, stream=None):
+        dgd_operator_apply(self.handle, x, y, n_rhs, stream)
+
+    def solve(self, points, sigma0, deltas, workspace=None, stream=None):
+        return dgd_eap_solve(self.handle, points, sigma0, deltas, workspace=workspace, stream=stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+class Run:
+    def __init__(self, op: Operator, points, sigma0, workspace=None, stream=None):
+        self._destroy = _lib.dgd_run_destroy
+        self.op = op
+        self.n = int(np.asarray(points).reshape(-1, 2).shape[0])
+        self.workspace = workspace
+        self.handle = dgd_run_create(op.handle, points, sigma0, workspace=workspace, stream=stream)
+
+    def advance(self, n_steps, dt_ms):
+        dgd_run_advance(self.handle, n_steps, dt_ms)
+
+    def moments(self, check=True):
+        return dgd_run_moments(self.handle, self.n, check)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,241 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Every case prints what it runs (flushed) before touching the GPU.
+Tolerances: FP64 paths 1e-10 relative on Sigma (Frobenius norm of the 2x2
+difference over the norm of the oracle's Sigma); FP32 paths 1e-4.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bounds, mesh as omesh, moments as omom, sipg
+from oracle import solve as osolve
+from oracle import timeint
+from workloads import config, make_geometry, start_points
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dgd():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    from paper_1907_06191_amd import dgd as d
+    return d
+
+
+def _nodal_transform(op_o, nodes):
+    """Block change of basis from the oracle's monomials in the centred cell
+    frame to nodal values at the library's nodes: T[o][i][k] = psi_k(node_i)."""
+    mons = sipg.monomials(op_o.p)
+    T = []
+    for o in (0, 1):
+        xi = nodes[o, :, 0] - 0.5
+        et = nodes[o, :, 1] - 0.5
+        T.append(np.stack([xi ** a * et ** b for (a, b) in mons], axis=1))
+    return T
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_V10_operator_extraction(dgd, p, prec):
+    """V10: apply the GPU operator to every unit vector and compare the dense
+    nodal matrix with the oracle's -M^-1 A after the change of basis."""
+    import torch
+    say(f"V10 operator extraction p={p} {prec}")
+    disks = np.array([[1.5, 2.5, 0.6], [4.2, 4.4, 0.7], [5.6, 0.4, 0.5]])
+    L, N, D = 6.0, 6, 1.7
+    mesh = dgd.Mesh(L, N, disks)
+    pr = dgd.DGD_FP64 if prec == "fp64" else dgd.DGD_FP32
+    op = dgd.Operator(mesh, p, D, 10.0, pr, dt_max_ms=1e-3)
+    npn, nodes, _ = op.info()
+    m = omesh.build_mesh(L, N, disks)
+    oo = sipg.assemble(m, p, D, 10.0)
+    E = m.n_elements
+    n = E * npn
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    x = torch.eye(n, dtype=dtype, device="cuda")
+    y = torch.zeros_like(x)
+    op.apply(x, y, n)
+    torch.cuda.synchronize()
+    Lg = y.double().cpu().numpy()
+    # element map library -> oracle
+    ci, cj, ori = mesh.elements()
+    key = {(int(a), int(b), int(c)): e for e, (a, b, c) in enumerate(zip(m.cell_i, m.cell_j, m.orient))}
+    perm = np.array([key[(int(a), int(b), int(c))] for a, b, c in zip(ci, cj, ori)])
+    T = _nodal_transform(oo, nodes)
+    Tb = np.zeros((n, n))
+    for e in range(E):
+        oe = perm[e]
+        Tb[e * npn:(e + 1) * npn, oe * npn:(oe + 1) * npn] = T[int(ori[e])]
+    Lo = oo.L.toarray()
+    Lref = Tb @ Lo @ np.linalg.inv(Tb)
+    scale = np.abs(Lref).max()
+    # FP64: the monomial-to-nodal change of basis of this test loses ~1e-11 at p = 3
+    tol = (1e-12 if p < 3 else 1e-10) if prec == "fp64" else 1e-6
+    err = np.abs(Lg - Lref).max() / scale
+    say(f"  max |L_gpu - L_oracle| / max|L| = {err:.2e}")
+    assert err < tol
+
+
+def _c1_setup():
+    c = config("C1")
+    g = make_geometry(c["L"], c["N"], c["geom_seed"], n_disks=c["n_disks"])
+    pts = start_points(g.disks, g.L, g.N, 1, np.random.default_rng(c["point_seed"]))
+    return c, g, pts
+
+
+def test_c1_parity_fp64(dgd):
+    """Small workload in full: P1 FP64 on the 64^2 grid, Delta = 1, 2, 5 ms,
+    the oracle's RK3 with the identical step schedule; 1e-10 on Sigma."""
+    c, g, pts = _c1_setup()
+    prob = osolve.prepare(g.L, g.N, g.disks, c["p"], c["D"], c["eta"])
+    dt = prob.dt["dt_nom"]
+    say(f"C1 parity FP64: {prob.op.mesh.n_elements} elements, dt={dt:.4e} ms")
+    ref = osolve.solve(prob, pts, c["sigma0"], c["deltas"], method="rk3")
+    mesh = dgd.Mesh(g.L, g.N, g.disks)
+    op = dgd.Operator(mesh, c["p"], c["D"], c["eta"], dgd.DGD_FP64, dt_max_ms=dt)
+    assert op.dt == dt
+    sig, mom = op.solve(pts, c["sigma0"], c["deltas"])
+    err = omom.rel_err(sig, omom.sigma_a(ref))
+    say(f"  rel err per Delta {err.ravel()}; mass {mom[..., 0].ravel()}")
+    assert err.max() < 1e-10
+    assert np.abs(mom[..., 0] - 1).max() < 1e-12
+    assert np.abs(mom - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+def _small_dense_case(nrhs=8, N=64, seed=7):
+    """A 12.5 um box at the C2 grid spacing (h = 100/512) and packing 0.6."""
+    h = 100.0 / 512
+    L = N * h
+    g = make_geometry(L, N, 19070619 + 900 + seed, phi=0.6)
+    pts = start_points(g.disks, g.L, g.N, nrhs, np.random.default_rng(19070619 + 901 + seed))
+    return g, pts
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_fp32_parity_dense_packing(dgd, p):
+    """FP32 state and operator, FP64 moments, on a dense packing at the C2
+    grid spacing: Sigma within 1e-4 of the oracle's exact flow (Chebyshev)
+    at Delta = 0.5 and 1 ms (about 22k and 44k RK3 steps for P2)."""
+    g, pts = _small_dense_case()
+    deltas = [0.5, 1.0]
+    prob = osolve.prepare(g.L, g.N, g.disks, p, 2.0, 10.0)
+    dt = prob.dt["dt_nom"]
+    say(f"FP32 parity p={p}: {prob.op.mesh.n_elements} elements, dt={dt:.3e}")
+    ref = osolve.solve(prob, pts, 0.3, deltas, method="cheb")
+    mesh = dgd.Mesh(g.L, g.N, g.disks)
+    op = dgd.Operator(mesh, p, 2.0, 10.0, dgd.DGD_FP32, dt_max_ms=dt)
+    sig, mom = op.solve(pts, 0.3, deltas)
+    err = omom.rel_err(sig, omom.sigma_a(ref))
+    say(f"  max rel err {err.max():.2e}, max |M0-1| {np.abs(mom[..., 0] - 1).max():.2e}")
+    assert err.max() < 1e-4
+
+
+def test_determinism_graphs_and_checkpoint(dgd):
+    """Two runs are bitwise equal (no atomics); graph replay equals plain
+    launches bitwise; a state saved and restored into a new run continues
+    bitwise like the uninterrupted run."""
+    g, pts = _small_dense_case(nrhs=4, N=32, seed=3)
+    prob = osolve.prepare(g.L, g.N, g.disks, 2, 2.0, 10.0)
+    dt = prob.dt["dt_nom"]
+    say("determinism / graphs / checkpoint, P2 FP32")
+    mesh = dgd.Mesh(g.L, g.N, g.disks)
+    op = dgd.Operator(mesh, 2, 2.0, 10.0, dgd.DGD_FP32, dt_max_ms=dt)
+    E = mesh.info()["n_active"]
+    nval = E * 6 * pts.shape[0]
+
+    def run(steps_list, graphs=True, restore=None):
+        dgd.dgd_set_option("graphs", 1 if graphs else 0)
+        r = dgd.Run(op, pts, 0.3)
+        if restore is not None:
+            dgd.dgd_run_set_state(r.handle, restore)
+        outs = []
+        for n in steps_list:
+            r.advance(n, dt)
+            outs.append(r.moments())
+        st = dgd.dgd_run_get_state(r.handle, nval, np.float32)
+        r.close()
+        dgd.dgd_set_option("graphs", 1)
+        return outs, st
+
+    a, sa = run([100, 37, 64])
+    b, sb = run([100, 37, 64])
+    c, sc = run([100, 37, 64], graphs=False)
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y)
+        assert np.array_equal(x, z)
+    assert np.array_equal(sa, sb) and np.array_equal(sa, sc)
+    # checkpoint after 137 steps, resume for 64
+    _, s137 = run([100, 37])
+    d, sd = run([64], restore=s137)
+    assert np.array_equal(sd, sa)
+    assert np.array_equal(d[-1], a[-1])
+
+
+def test_auto_dt_is_stable(dgd):
+    """The library's own step rule (device power iteration) stays inside the
+    RK3 stability interval for the oracle's largest eigenvalue."""
+    for p in (1, 2, 3):
+        g, _ = _small_dense_case(nrhs=1, N=32, seed=11)
+        m = omesh.build_mesh(g.L, g.N, g.disks)
+        oo = sipg.assemble(m, p, 2.0, 10.0)
+        lam = bounds.lambda_max(oo)
+        mesh = dgd.Mesh(g.L, g.N, g.disks)
+        op = dgd.Operator(mesh, p, 2.0, 10.0, dgd.DGD_FP32)
+        dt, lam_gpu = dgd.dgd_operator_dt(op.handle)
+        say(f"auto dt p={p}: lambda oracle {lam:.6e} gpu {lam_gpu:.6e} dt {dt:.4e}")
+        assert abs(lam_gpu / lam - 1) < 0.02
+        assert dt * lam <= bounds.X_RK3
+
+
+def test_error_paths(dgd):
+    """ENOTFREE for a start point in a removed cell or outside the box,
+    EINVAL for a bad Delta list or a too small workspace (ENOMEM)."""
+    import torch
+    disks = np.array([[2.0, 2.0, 1.0]])
+    mesh = dgd.Mesh(4.0, 8, disks)
+    op = dgd.Operator(mesh, 1, 2.0, 10.0, dgd.DGD_FP32, dt_max_ms=1e-3)
+    say("error paths")
+    for bad in ([[2.0, 2.0]], [[-0.1, 1.0]], [[1.0, 4.0]]):
+        with pytest.raises(dgd.DGDError) as e:
+            op.solve(np.array(bad), 0.3, [0.01])
+        assert e.value.code == dgd.DGD_ENOTFREE
+    for deltas in ([0.02, 0.01], [0.0], [0.01, 0.01]):
+        with pytest.raises(dgd.DGDError) as e:
+            op.solve(np.array([[0.3, 0.3]]), 0.3, deltas)
+        assert e.value.code == dgd.DGD_EINVAL
+    ws = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(dgd.DGDError) as e:
+        op.solve(np.array([[0.3, 0.3]]), 0.3, [0.01], workspace=ws)
+    assert e.value.code == dgd.DGD_ENOMEM
+    # an explicitly unstable step is caught by the mass / finiteness check
+    op2 = dgd.Operator(mesh, 1, 2.0, 10.0, dgd.DGD_FP32, dt_max_ms=0.05)
+    with pytest.raises(dgd.DGDError) as e:
+        op2.solve(np.array([[0.3, 0.3]]), 0.3, [20.0])
+    assert e.value.code == dgd.DGD_EUNSTABLE
+
+
+def test_torch_workspace_and_stream(dgd):
+    """A torch-owned workspace and stream give the same result as the
+    library's own allocation."""
+    import torch
+    c, g, pts = _c1_setup()
+    prob = osolve.prepare(g.L, g.N, g.disks, c["p"], c["D"], c["eta"])
+    dt = prob.dt["dt_nom"]
+    mesh = dgd.Mesh(g.L, g.N, g.disks)
+    op = dgd.Operator(mesh, c["p"], c["D"], c["eta"], dgd.DGD_FP64, dt_max_ms=dt)
+    say("torch workspace / stream")
+    ws = torch.empty(op.workspace_size(1), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    a, _ = op.solve(pts, c["sigma0"], [0.3], workspace=ws, stream=s)
+    b, _ = op.solve(pts, c["sigma0"], [0.3])
+    assert np.array_equal(a, b)
