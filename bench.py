@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--p", type=int, default=None, help="override polynomial degree")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, copy 1 GiB device-to-device once (a plain "
+                         "copy kernel of known size, to calibrate HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -164,6 +167,14 @@ def main():
         },
     }
     run.close()
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = {"read": a.numel() * 4, "write": b.numel() * 4}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(g, pts, p, c["D"], c["eta"], c["sigma0"], dt, lam,

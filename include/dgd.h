@@ -66,9 +66,11 @@ const char* dgd_last_error(void);
  * (h = L / n_cells) with the disks removed (sections 2.2 and 3.3).
  *   disks: host float64 [n_disks][3] = (cx, cy, r); disks may cross the box
  *          edge; n_disks may be 0 (disks may then be NULL).
- * Elements are ordered cell-major (row j slow, column i fast), the lower
- * right triangle T0 of a cell before its upper left triangle T1.  The mesh
- * tables are uploaded to the current HIP device.  *out is owned by the
+ * Elements are ordered by cells in vertical strips of "mesh_strip" columns
+ * (see dgd_set_option; default 64), each strip row by row, the lower right
+ * triangle T0 of a cell before its upper left triangle T1; dgd_mesh_elements
+ * reports the order.  The element table goes to the current HIP device when
+ * the first operator is built on the mesh.  *out is owned by the
  * caller and released with dgd_mesh_destroy.
  * Errors: EINVAL (L <= 0, n_cells < 1 or > 16384, n_disks < 0, NULL out),
  * ENOMEM, EDEVICE.
@@ -187,6 +189,8 @@ int dgd_eap_solve(dgd_op* op, const double* points, int32_t n_points, double sig
  *   "stage_epw"    elements walked by each wave of the stage kernel, 1..256
  *   "stage_waves"  waves per workgroup of the stage kernel, 1..4
  *   "xcd_remap"    1 = each XCD sweeps one contiguous band of elements
+ *   "mesh_strip"   element order of meshes created afterwards: vertical strips
+ *                  of this many cell columns, each row-major (0 = plain rows)
  * Errors: EINVAL for an unknown name or a value out of range. */
 int dgd_set_option(const char* name, int64_t value);
 

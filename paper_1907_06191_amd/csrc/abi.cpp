@@ -35,7 +35,8 @@ struct Options {
   int64_t graph_steps = 32;
   int stage_epw = 1;        // elements per wave in the stage kernel
   int stage_waves = 4;      // waves per workgroup in the stage kernel
-  bool xcd_remap = false;   // XCD-banded block order (measured: no gain at one element per wave)
+  bool xcd_remap = true;    // XCD-banded block order
+  int mesh_strip = 64;      // element order: vertical strips of this many cell columns (0: rows)
 };
 Options g_opt;
 
@@ -249,6 +250,9 @@ int dgd_set_option(const char* name, int64_t value) {
       g_opt.stage_waves = (int)value;
     } else if (n == "xcd_remap") {
       g_opt.xcd_remap = value != 0;
+    } else if (n == "mesh_strip") {
+      if (value < 0 || value > 16384) fail(DGD_EINVAL, "mesh_strip must be in [0, 16384]");
+      g_opt.mesh_strip = (int)value;
     } else fail(DGD_EINVAL, "unknown option " + n);
     return DGD_OK;
   });
@@ -267,7 +271,7 @@ int dgd_mesh_create(double L_um, int32_t n_cells, const double* disks, int32_t n
         if (!std::isfinite(disks[3 * d + k])) fail(DGD_EINVAL, "disk list holds a non-finite value");
     auto* m = new dgd_mesh();
     try {
-      build_mesh_host(L_um, n_cells, disks, n_disks, m->host);
+      build_mesh_host(L_um, n_cells, disks, n_disks, g_opt.mesh_strip, m->host);
       const int64_t E = m->host.n_elements();
       if (E > ((int64_t)1 << 31) - 1) fail(DGD_EINVAL, "too many elements");
       std::vector<int4> pk(std::max<int64_t>(E, 1));

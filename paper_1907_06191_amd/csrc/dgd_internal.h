@@ -57,7 +57,7 @@ struct RefElem {
 
 RefElem build_ref_elem(int p, double eta);
 std::vector<double> build_ic_quadrature(const RefElem& R, int n);
-void build_mesh_host(double L, int N, const double* disks, int n_disks, MeshHost& m);
+void build_mesh_host(double L, int N, const double* disks, int n_disks, int strip, MeshHost& m);
 
 }  // namespace dgd
 

@@ -19,7 +19,7 @@
 
 namespace dgd {
 
-void build_mesh_host(double L, int N, const double* disks, int n_disks, MeshHost& m) {
+void build_mesh_host(double L, int N, const double* disks, int n_disks, int strip, MeshHost& m) {
   m.L = L;
   m.N = N;
   m.h = L / N;
@@ -39,12 +39,18 @@ void build_mesh_host(double L, int N, const double* disks, int n_disks, MeshHost
         if (dx * dx + dy * dy < r * r) m.active_cell[(size_t)j * N + i] = 0;
       }
   }
-  // rank active cells, cell-major
+  // rank active cells: vertical strips of `strip` columns, each strip
+  // row-major (j slow, i fast); strip <= 0 or >= N gives plain row-major.
+  // With the stage kernel's XCD-banded block order, each XCD then sweeps a
+  // few strips top to bottom and the rows above and below the one in flight
+  // (the vertical face neighbours) stay in its L2.
+  const int W = (strip <= 0 || strip >= N) ? N : strip;
   std::vector<int64_t> rank((size_t)N * N, -1);
   int64_t nc = 0;
-  for (int j = 0; j < N; ++j)
-    for (int i = 0; i < N; ++i)
-      if (m.active_cell[(size_t)j * N + i]) rank[(size_t)j * N + i] = nc++;
+  for (int s0 = 0; s0 < N; s0 += W)
+    for (int j = 0; j < N; ++j)
+      for (int i = s0; i < std::min(N, s0 + W); ++i)
+        if (m.active_cell[(size_t)j * N + i]) rank[(size_t)j * N + i] = nc++;
   const int64_t E = 2 * nc;
   m.ci.resize(E);
   m.cj.resize(E);

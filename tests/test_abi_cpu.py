@@ -36,11 +36,16 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("name", ["C1", "C4"])
-def test_host_mesh_matches_oracle_mesh(name):
+@pytest.mark.parametrize("strip", [0, 64, 24])
+def test_host_mesh_matches_oracle_mesh(name, strip):
     from paper_1907_06191_amd import dgd
     c = config(name)
     g = make_geometry(c["L"], c["N"], c["geom_seed"], phi=c["phi"], n_disks=c["n_disks"])
-    m = dgd.Mesh(g.L, g.N, g.disks)
+    dgd.dgd_set_option("mesh_strip", strip)
+    try:
+        m = dgd.Mesh(g.L, g.N, g.disks)
+    finally:
+        dgd.dgd_set_option("mesh_strip", 64)
     o = omesh.build_mesh(g.L, g.N, g.disks)
     info = m.info()
     assert info["n_active"] == o.n_elements
@@ -48,7 +53,16 @@ def test_host_mesh_matches_oracle_mesh(name):
     assert info["n_components"] == o.n_components()
     assert abs(info["removed_fraction"] - o.removed_fraction()) < 1e-15
     ci, cj, ori = m.elements()
-    assert (ci == o.cell_i).all() and (cj == o.cell_j).all() and (ori == o.orient).all()
+    if strip == 0 or strip >= g.N:
+        # plain row-major order is the oracle's own order
+        assert (ci == o.cell_i).all() and (cj == o.cell_j).all() and (ori == o.orient).all()
+    # same set of (cell, orientation), each once
+    key = lambda i, j, t: (np.asarray(j, np.int64) * g.N + np.asarray(i)) * 2 + np.asarray(t)  # noqa: E731
+    assert np.array_equal(np.sort(key(ci, cj, ori)), np.sort(key(o.cell_i, o.cell_j, o.orient)))
+    if strip:
+        w = strip
+        strip_of = ci // w
+        assert (np.diff(strip_of) >= 0).all()     # strips in order
 
 
 def test_host_mesh_edge_cases():
