@@ -54,6 +54,7 @@ extern "C" {
 typedef struct dgd_mesh dgd_mesh;
 typedef struct dgd_op dgd_op;
 typedef struct dgd_run dgd_run;
+typedef struct dgd_batch dgd_batch;
 
 /* Library version as 10000*major + 100*minor + patch. */
 int dgd_version(void);
@@ -72,7 +73,7 @@ const char* dgd_last_error(void);
  * reports the order.  The element table goes to the current HIP device when
  * the first operator is built on the mesh.  *out is owned by the
  * caller and released with dgd_mesh_destroy.
- * Errors: EINVAL (L <= 0, n_cells < 1 or > 16384, n_disks < 0, NULL out),
+ * Errors: EINVAL (L <= 0, n_cells < 1 or > 16383, n_disks < 0, NULL out),
  * ENOMEM, EDEVICE.
  */
 int dgd_mesh_create(double L_um, int32_t n_cells, const double* disks, int32_t n_disks,
@@ -183,12 +184,46 @@ int dgd_eap_solve(dgd_op* op, const double* points, int32_t n_points, double sig
                   const double* deltas_ms, int32_t n_deltas, double* sigma_out,
                   double* moments_out, void* d_ws, size_t ws_bytes, void* hip_stream);
 
+/*
+ * Batched solve (section 4.1 over many substrates; the paper's timing table
+ * runs 37 start points one after another): n_geoms operators, each on its
+ * own mesh, with n_points start points each.  The operators must share h,
+ * D, eta and precision; they are grouped by p, and each group advances as
+ * one run over the concatenated element tables of its geometries (one
+ * fused kernel launch per RK stage for the whole group, replayed from HIP
+ * graphs), with the smallest nominal step of its members.
+ *   points: host float64 [n_geoms][n_points][2].
+ *   d_ws: NULL or >= dgd_batch_workspace_size bytes of device memory.
+ */
+int dgd_batch_workspace_size(dgd_op* const* ops, int32_t n_geoms, int32_t n_points, size_t* bytes);
+int dgd_batch_create(dgd_op* const* ops, int32_t n_geoms, const double* points, int32_t n_points,
+                     double sigma0_um, void* d_ws, size_t ws_bytes, void* hip_stream,
+                     dgd_batch** out);
+/* Groups: count, and per group p, number of geometries, step (ms) and active
+ * DoF per right-hand side.  Output arrays may be NULL. */
+int dgd_batch_groups(const dgd_batch* batch, int32_t* n_groups, int32_t* group_p,
+                     int32_t* group_size, double* group_dt, int64_t* group_dof);
+/* Advance one group by n_steps SSP-RK3 steps of dt_ms. */
+int dgd_batch_advance(dgd_batch* batch, int32_t group, int64_t n_steps, double dt_ms);
+/* FP64 moments, host [n_geoms][n_points][6]; EUNSTABLE as dgd_run_moments. */
+int dgd_batch_moments(dgd_batch* batch, double* moments_out);
+void dgd_batch_destroy(dgd_batch* batch);
+
+/* Whole batched solve through the Delta list (landing schedule per group);
+ * sigma_out host [n_geoms][n_points][n_deltas][3], moments_out NULL or
+ * [n_geoms][n_points][n_deltas][6].  Synchronous. */
+int dgd_eap_solve_batch(dgd_op* const* ops, int32_t n_geoms, const double* points,
+                        int32_t n_points, double sigma0_um, const double* deltas_ms,
+                        int32_t n_deltas, double* sigma_out, double* moments_out, void* d_ws,
+                        size_t ws_bytes, void* hip_stream);
+
 /* Runtime options (process-wide; read when a run is created or advanced):
  *   "graphs"       1 = replay steps from captured HIP graphs, 0 = plain launches
  *   "graph_steps"  steps captured per graph, 1..4096
  *   "stage_epw"    elements walked by each wave of the stage kernel, 1..256
  *   "stage_waves"  waves per workgroup of the stage kernel, 1..4
  *   "xcd_remap"    1 = each XCD sweeps one contiguous band of elements
+ *   "stage_grid"   > 0: persistent stage kernel with this many workgroups
  *   "mesh_strip"   element order of meshes created afterwards: vertical strips
  *                  of this many cell columns, each row-major (0 = plain rows)
  * Errors: EINVAL for an unknown name or a value out of range. */

@@ -1,4 +1,4 @@
-// C-ABI of libdgd: meshes, operators, runs and the whole solve.
+// C-ABI of libdgd: meshes, operators, runs, batches and the whole solve.
 //
 // The solve follows section 4.1 of the paper: one diffusion problem per
 // start point, carried to each diffusion time, and the covariance of the
@@ -36,15 +36,22 @@ struct Options {
   int stage_epw = 1;        // elements per wave in the stage kernel
   int stage_waves = 4;      // waves per workgroup in the stage kernel
   bool xcd_remap = true;    // XCD-banded block order
+  int64_t stage_grid = 0;   // > 0: persistent stage kernel with this many workgroups
   int mesh_strip = 64;      // element order: vertical strips of this many cell columns (0: rows)
 };
 Options g_opt;
 
-Shape stage_shape(int64_t E) { return element_shape(E, g_opt.stage_epw, g_opt.stage_waves, g_opt.xcd_remap); }
+constexpr int kEpwReduce = 16;      // reduction kernels: 16 elements per wave, 4 waves
+constexpr int kReducePer = 64;      // elements per reduction block
+constexpr double kCutoff = 12.0;    // initial pulse evaluated within 12 sigma0 of x0
+constexpr int kQuadN = 12;          // 12 x 12 collapsed Gauss-Legendre points per triangle
+constexpr int kPadCell = 0x3fff;    // cell index of batch padding elements
+constexpr int kMaxCells = 16383;
 
-constexpr int kEpwReduce = 16;
-constexpr double kCutoff = 12.0;   // initial pulse evaluated within 12 sigma0 of x0
-constexpr int kQuadN = 12;         // 12 x 12 collapsed Gauss-Legendre points per triangle
+Shape stage_shape(int64_t E) {
+  return element_shape(E, g_opt.stage_epw, g_opt.stage_waves, g_opt.xcd_remap, g_opt.stage_grid);
+}
+Shape reduce_shape(int64_t E) { return element_shape(E, kEpwReduce, 4, true, 0); }
 
 template <typename F>
 int guarded(F&& f) {
@@ -72,8 +79,8 @@ size_t state_bytes(int prec) { return prec == DGD_FP64 ? 8 : 4; }
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Real root of x^3/6 - x^2/2 + x - 2 = 0: |R(-x)| = 1 edge of the SSP-RK3
-// stability interval on the negative real axis.
+// Real root of x^3/6 - x^2/2 + x - 2 = 0: the edge of the SSP-RK3 stability
+// interval on the negative real axis, where R(z) = 1 + z + z^2/2 + z^3/6 = -1.
 double rk3_limit() {
   double x = 2.5;
   for (int i = 0; i < 60; ++i) {
@@ -85,12 +92,39 @@ double rk3_limit() {
 }
 
 template <typename T>
-void* upload(const std::vector<double>& v) {
-  std::vector<T> t(v.begin(), v.end());
+void* upload(const std::vector<T>& v) {
   void* d = nullptr;
-  DGD_HIP_CHECK(hipMalloc(&d, t.size() * sizeof(T)));
-  DGD_HIP_CHECK(hipMemcpy(d, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice));
+  DGD_HIP_CHECK(hipMalloc(&d, std::max<size_t>(v.size(), 1) * sizeof(T)));
+  if (!v.empty()) DGD_HIP_CHECK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   return d;
+}
+
+// The element table goes to the device on first use (operator build), so
+// that meshes can be built and inspected on a host without a GPU.
+void ensure_mesh_on_device(const dgd_mesh* cm) {
+  dgd_mesh* m = const_cast<dgd_mesh*>(cm);
+  if (m->d_elem) return;
+  DGD_HIP_CHECK(hipGetDevice(&m->device));
+  m->d_elem = (int4*)upload(m->packed);
+}
+
+RunTarget plain_target(const dgd_op* op) {
+  RunTarget t;
+  t.elem = op->mesh->d_elem;
+  t.E = op->mesh->host.n_elements();
+  t.np = op->ref.np;
+  t.prec = op->precision;
+  t.S = op->d_S;
+  t.N = op->d_N;
+  t.D = op->D;
+  t.h = op->mesh->host.h;
+  t.W = op->d_W;
+  t.Minv = op->d_Minv;
+  t.quad = op->d_quad;
+  t.nq = op->nq;
+  t.G = 1;
+  t.nblk_red = reduce_shape(t.E).blocks;
+  return t;
 }
 
 // Largest eigenvalue of -M^-1 A (dimensionless) by power iteration in FP64
@@ -102,7 +136,6 @@ double power_lambda(dgd_op* op, int iters) {
   const int np = op->ref.np;
   const int R = 16;
   const int64_t n = E * np * R;
-  // row-sum bound of the dimensionless operator
   double g = 0;
   for (int o = 0; o < 2; ++o)
     for (int mask = 0; mask < 8; ++mask)
@@ -114,37 +147,37 @@ double power_lambda(dgd_op* op, int iters) {
             for (int j = 0; j < np; ++j) s += std::fabs(op->ref.Nb[((o * 3 + f) * np + i) * np + j]);
         g = std::max(g, s);
       }
-  void* S64 = upload<double>(op->ref.S);
-  void* N64 = upload<double>(op->ref.Nb);
-  double* Mass = (double*)upload<double>(op->ref.Mass);
+  double* Mass = (double*)upload(op->ref.Mass);
   double *x = nullptr, *y = nullptr, *part = nullptr, *red = nullptr;
+  int* bs = nullptr;
   const Shape sh = stage_shape(E);
-  const Shape shr = element_shape(E, kEpwReduce);
+  const Shape shr = reduce_shape(E);
   auto cleanup = [&]() {
-    (void)hipFree(S64); (void)hipFree(N64); (void)hipFree(Mass); (void)hipFree(x);
-    (void)hipFree(y); (void)hipFree(part); (void)hipFree(red);
+    (void)hipFree(Mass); (void)hipFree(x); (void)hipFree(y); (void)hipFree(part);
+    (void)hipFree(red); (void)hipFree(bs);
   };
   try {
     DGD_HIP_CHECK(hipMalloc(&x, n * sizeof(double)));
     DGD_HIP_CHECK(hipMalloc(&y, n * sizeof(double)));
-    DGD_HIP_CHECK(hipMalloc(&part, shr.nblk() * R * 6 * sizeof(double)));
+    DGD_HIP_CHECK(hipMalloc(&part, shr.blocks * R * 6 * sizeof(double)));
     DGD_HIP_CHECK(hipMalloc(&red, R * 6 * sizeof(double)));
+    bs = (int*)upload(std::vector<int>{0, (int)shr.blocks});
     hipStream_t st = nullptr;
     launch_fill_random(x, n, 0x1907061900ull, st);
     const int4* elem = mesh->d_elem;
     for (int it = 0; it < iters; ++it) {
-      launch_stage(DGD_FP64, np, x, nullptr, y, elem, E, S64, N64, 0, 0.0, 1.0 / g, R, sh, st);
+      launch_stage(DGD_FP64, np, x, nullptr, y, elem, E, op->d_S, op->d_N, 0, 0.0, 1.0 / g, R, sh, st);
       std::swap(x, y);
     }
     DGD_HIP_CHECK(hipGetLastError());
     // y = L x (unscaled); lambda = -(x, M y) / (x, M x)
-    launch_stage(DGD_FP64, np, x, nullptr, y, elem, E, S64, N64, 0, 0.0, 1.0, R, sh, st);
+    launch_stage(DGD_FP64, np, x, nullptr, y, elem, E, op->d_S, op->d_N, 0, 0.0, 1.0, R, sh, st);
     std::vector<double> xmy(R * 6), xmx(R * 6);
     launch_dot_mass(np, x, y, elem, E, Mass, R, shr, part, st);
-    launch_reduce(part, (int)shr.nblk(), R, red, st);
+    launch_reduce(part, bs, 1, R, red, st);
     DGD_HIP_CHECK(hipMemcpy(xmy.data(), red, R * 6 * sizeof(double), hipMemcpyDeviceToHost));
     launch_dot_mass(np, x, x, elem, E, Mass, R, shr, part, st);
-    launch_reduce(part, (int)shr.nblk(), R, red, st);
+    launch_reduce(part, bs, 1, R, red, st);
     DGD_HIP_CHECK(hipMemcpy(xmx.data(), red, R * 6 * sizeof(double), hipMemcpyDeviceToHost));
     double lam = 0;
     for (int r = 0; r < R; ++r)
@@ -157,23 +190,110 @@ double power_lambda(dgd_op* op, int iters) {
   }
 }
 
+// ---------------------------------------------------------------- runs ----
+
+void ws_layout(const RunTarget& t, int R, size_t* total, size_t off[7]) {
+  const size_t st = align256((size_t)t.E * t.np * R * state_bytes(t.prec));
+  size_t o = 0;
+  off[0] = o; o += st;                                            // U
+  off[1] = o; o += st;                                            // U1
+  off[2] = o; o += st;                                            // U2
+  off[3] = o; o += align256((size_t)t.G * R * 2 * 8);             // x0
+  off[4] = o; o += align256((size_t)t.nblk_red * R * 6 * 8);      // partials
+  off[5] = o; o += align256((size_t)t.G * R * 6 * 8);             // moments
+  off[6] = o; o += align256((size_t)(t.G + 1) * sizeof(int));     // block ranges
+  *total = o;
+}
+
+void run_destroy(dgd_run* run) {
+  if (!run) return;
+  if (run->stream) (void)hipStreamSynchronize(run->stream);
+  for (auto& kv : run->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (run->own_ws) (void)hipFree(run->ws);
+  if (run->own_stream) (void)hipStreamDestroy(run->stream);
+  delete run;
+}
+
+// Allocate (or adopt) the workspace, copy the start points, and project
+// the initial pulse of every (geometry, start point).
+dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, void* d_ws,
+                    size_t ws_bytes, void* hip_stream) {
+  size_t total, off[7];
+  ws_layout(t, R, &total, off);
+  auto* run = new dgd_run();
+  try {
+    run->t = t;
+    run->R = R;
+    run->x0.assign(x0, x0 + (size_t)t.G * R * 2);
+    if (d_ws) {
+      if (ws_bytes < total) fail(DGD_ENOMEM, "workspace smaller than the size the library reports");
+      run->ws = d_ws;
+      run->ws_bytes = ws_bytes;
+    } else {
+      DGD_HIP_CHECK(hipMalloc(&run->ws, total));
+      run->own_ws = true;
+      run->ws_bytes = total;
+    }
+    if (hip_stream) {
+      run->stream = (hipStream_t)hip_stream;
+    } else {
+      DGD_HIP_CHECK(hipStreamCreateWithFlags(&run->stream, hipStreamNonBlocking));
+      run->own_stream = true;
+    }
+    char* base = (char*)run->ws;
+    run->U = base + off[0];
+    run->U1 = base + off[1];
+    run->U2 = base + off[2];
+    run->d_x0 = (double*)(base + off[3]);
+    run->d_part = (double*)(base + off[4]);
+    run->d_mom = (double*)(base + off[5]);
+    run->d_blk_start = (int*)(base + off[6]);
+    if (!t.blk_start) {
+      // one geometry: all reduction blocks
+      const int bs[2] = {0, (int)t.nblk_red};
+      DGD_HIP_CHECK(hipMemcpyAsync(run->d_blk_start, bs, sizeof(bs), hipMemcpyHostToDevice,
+                                   run->stream));
+    } else {
+      DGD_HIP_CHECK(hipMemcpyAsync(run->d_blk_start, t.blk_start, (size_t)(t.G + 1) * sizeof(int),
+                                   hipMemcpyDeviceToDevice, run->stream));
+    }
+    DGD_HIP_CHECK(hipMemcpyAsync(run->d_x0, run->x0.data(), run->x0.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, run->stream));
+    const Shape shr = reduce_shape(t.E);
+    launch_ic_mass(t.np, t.elem, t.E, t.quad, t.nq, run->d_x0, t.blk_geom, sigma0, t.h, kCutoff, R,
+                   shr, run->d_part, run->stream);
+    launch_reduce(run->d_part, run->d_blk_start, t.G, R, run->d_mom, run->stream);
+    launch_ic_project(t.prec == DGD_FP64 ? 0 : 1, t.np, t.elem, t.E, t.quad, t.nq, t.Minv,
+                      run->d_x0, t.blk_geom, run->d_mom, sigma0, t.h, kCutoff, R, shr, run->U,
+                      run->stream);
+    DGD_HIP_CHECK(hipGetLastError());
+    std::vector<double> mass((size_t)t.G * R * 6);
+    DGD_HIP_CHECK(hipMemcpyAsync(mass.data(), run->d_mom, mass.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, run->stream));
+    DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+    for (int k = 0; k < t.G * R; ++k)
+      if (!(mass[(size_t)k * 6] > 0) || !std::isfinite(mass[(size_t)k * 6]))
+        fail(DGD_ENOTFREE, "start point " + std::to_string(k) + " has no pulse mass on active cells");
+  } catch (...) {
+    run_destroy(run);
+    throw;
+  }
+  return run;
+}
+
 void run_stage_steps(dgd_run* run, int64_t n, double dt) {
-  dgd_op* op = run->op;
-  const dgd_mesh* mesh = op->mesh;
-  const int64_t E = mesh->host.n_elements();
-  const int np = op->ref.np;
-  const double h = mesh->host.h;
-  const double gam = dt * op->D / (h * h);
-  const Shape sh = stage_shape(E);
-  const int pr = op->precision == DGD_FP64 ? 0 : 1;
+  const RunTarget& t = run->t;
+  const double gam = dt * t.D / (t.h * t.h);
+  const Shape sh = stage_shape(t.E);
+  const int pr = t.prec == DGD_FP64 ? 0 : 1;
   for (int64_t s = 0; s < n; ++s) {
     // Shu-Osher SSP-RK3 as corrections of u^n:
     //   u1 = u + dt L u;  u2 = u + 1/4 (u1 - u) + 1/4 dt L u1;  u' = u + 2/3 (u2 - u) + 2/3 dt L u2
-    launch_stage(pr, np, run->U, nullptr, run->U1, mesh->d_elem, E, op->d_S, op->d_N, 1, 0.0, gam,
+    launch_stage(pr, t.np, run->U, nullptr, run->U1, t.elem, t.E, t.S, t.N, 1, 0.0, gam, run->R,
+                 sh, run->stream);
+    launch_stage(pr, t.np, run->U1, run->U, run->U2, t.elem, t.E, t.S, t.N, 1, 0.25, 0.25 * gam,
                  run->R, sh, run->stream);
-    launch_stage(pr, np, run->U1, run->U, run->U2, mesh->d_elem, E, op->d_S, op->d_N, 1, 0.25,
-                 0.25 * gam, run->R, sh, run->stream);
-    launch_stage(pr, np, run->U2, run->U, run->U, mesh->d_elem, E, op->d_S, op->d_N, 1, 2.0 / 3.0,
+    launch_stage(pr, t.np, run->U2, run->U, run->U, t.elem, t.E, t.S, t.N, 1, 2.0 / 3.0,
                  2.0 / 3.0 * gam, run->R, sh, run->stream);
   }
 }
@@ -196,31 +316,122 @@ hipGraphExec_t step_graph(dgd_run* run, int64_t n, double dt) {
   return ex;
 }
 
-// The element table goes to the device on first use (operator build), so
-// that meshes can be built and inspected on a host without a GPU.
-void ensure_mesh_on_device(const dgd_mesh* cm) {
-  dgd_mesh* m = const_cast<dgd_mesh*>(cm);
-  if (m->d_elem) return;
-  DGD_HIP_CHECK(hipGetDevice(&m->device));
-  DGD_HIP_CHECK(hipMalloc(&m->d_elem, m->packed.size() * sizeof(int4)));
-  DGD_HIP_CHECK(hipMemcpy(m->d_elem, m->packed.data(), m->packed.size() * sizeof(int4),
-                          hipMemcpyHostToDevice));
+void run_advance(dgd_run* run, int64_t n_steps, double dt) {
+  if (n_steps < 0) fail(DGD_EINVAL, "n_steps must be >= 0");
+  if (!(dt > 0) || !std::isfinite(dt)) fail(DGD_EINVAL, "dt must be positive");
+  if (n_steps == 0) return;
+  const int64_t G = g_opt.graph_steps;
+  int64_t left = n_steps;
+  if (g_opt.graphs && left >= G) {
+    hipGraphExec_t ex = step_graph(run, G, dt);
+    while (left >= G) {
+      DGD_HIP_CHECK(hipGraphLaunch(ex, run->stream));
+      left -= G;
+    }
+  }
+  run_stage_steps(run, left, dt);
+  DGD_HIP_CHECK(hipGetLastError());
+  run->t_ms += n_steps * dt;
 }
 
-void ws_layout(const dgd_op* op, int R, size_t* total, size_t off[6], int* nblk) {
-  const int64_t E = op->mesh->host.n_elements();
-  const size_t sb = state_bytes(op->precision);
-  const size_t st = align256((size_t)E * op->ref.np * R * sb);
-  const Shape shr = element_shape(E, kEpwReduce);
-  *nblk = (int)shr.nblk();
-  size_t o = 0;
-  off[0] = o; o += st;                                     // U
-  off[1] = o; o += st;                                     // U1
-  off[2] = o; o += st;                                     // U2
-  off[3] = o; o += align256((size_t)R * 2 * 8);            // x0
-  off[4] = o; o += align256((size_t)shr.nblk() * R * 6 * 8);  // partials
-  off[5] = o; o += align256((size_t)R * 6 * 8);            // moments
-  *total = o;
+// FP64 moments [G][R][6]; returns DGD_EUNSTABLE (moments filled anyway) on a
+// non-finite value or mass drift beyond the precision's tolerance.
+int run_moments(dgd_run* run, double* out, std::string* why) {
+  const RunTarget& t = run->t;
+  const Shape shr = reduce_shape(t.E);
+  launch_moments(t.prec == DGD_FP64 ? 0 : 1, t.np, run->U, t.elem, t.E, t.W, run->d_x0,
+                 t.blk_geom, t.h, run->R, shr, run->d_part, run->stream);
+  launch_reduce(run->d_part, run->d_blk_start, t.G, run->R, run->d_mom, run->stream);
+  DGD_HIP_CHECK(hipGetLastError());
+  const size_t n = (size_t)t.G * run->R;
+  DGD_HIP_CHECK(hipMemcpyAsync(out, run->d_mom, n * 6 * sizeof(double), hipMemcpyDeviceToHost,
+                               run->stream));
+  DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+  const double tol = t.prec == DGD_FP64 ? 1e-9 : 1e-3;
+  for (size_t k = 0; k < n; ++k) {
+    for (int c = 0; c < 6; ++c)
+      if (!std::isfinite(out[k * 6 + c])) {
+        *why = "non-finite moment for start point " + std::to_string(k);
+        return DGD_EUNSTABLE;
+      }
+    if (std::fabs(out[k * 6] - 1.0) > tol) {
+      *why = "mass drift beyond tolerance for start point " + std::to_string(k);
+      return DGD_EUNSTABLE;
+    }
+  }
+  return DGD_OK;
+}
+
+void check_points(const MeshHost& mh, const double* points, int n, int offset = 0) {
+  for (int r = 0; r < n; ++r) {
+    const double x = points[2 * r], y = points[2 * r + 1];
+    if (!std::isfinite(x) || !std::isfinite(y) || x < 0 || y < 0 || x >= mh.L || y >= mh.L)
+      fail(DGD_ENOTFREE, "start point " + std::to_string(offset + r) + " lies outside the box");
+    const int i = std::min(mh.N - 1, (int)(x / mh.h)), j = std::min(mh.N - 1, (int)(y / mh.h));
+    if (!mh.active_cell[(size_t)j * mh.N + i])
+      fail(DGD_ENOTFREE, "start point " + std::to_string(offset + r) + " lies in a removed cell");
+  }
+}
+
+std::vector<std::pair<int64_t, double>> schedule(const double* deltas, int n, double dt_nom) {
+  std::vector<std::pair<int64_t, double>> s;
+  double prev = 0;
+  for (int k = 0; k < n; ++k) {
+    if (!std::isfinite(deltas[k]) || !(deltas[k] > prev))
+      fail(DGD_EINVAL, "Delta list must be finite, positive and strictly increasing");
+    const double span = deltas[k] - prev;
+    int64_t m = (int64_t)std::ceil(span / dt_nom - 1e-9);
+    if (m < 1) m = 1;
+    s.emplace_back(m, span / (double)m);
+    prev = deltas[k];
+  }
+  return s;
+}
+
+// ------------------------------------------------------------- batches ----
+
+void batch_destroy(dgd_batch* b) {
+  if (!b) return;
+  for (auto& g : b->groups) {
+    run_destroy(g.run);
+    (void)hipFree(g.d_elem);
+    (void)hipFree(g.d_blk_geom);
+    (void)hipFree(g.d_blk_start);
+  }
+  delete b;
+}
+
+// Group geometries by p (each group shares one step size).
+void batch_plan(dgd_batch* b) {
+  for (int g = 0; g < b->G; ++g) {
+    const int p = b->ops[g]->ref.p;
+    auto it = std::find_if(b->groups.begin(), b->groups.end(),
+                           [&](const dgd_batch::Group& x) { return x.p == p; });
+    if (it == b->groups.end()) {
+      b->groups.emplace_back();
+      b->groups.back().p = p;
+      it = b->groups.end() - 1;
+    }
+    it->geoms.push_back(g);
+  }
+}
+
+// Target and workspace bytes of a group: its geometries' element tables
+// concatenated, each padded to whole reduction blocks.
+size_t batch_group_bytes(const dgd_batch::Group& grp, const dgd_batch* b, RunTarget* t_out) {
+  RunTarget t = plain_target(b->ops[grp.geoms[0]]);
+  int64_t E = 0;
+  for (int g : grp.geoms) {
+    const int64_t Eg = b->ops[g]->mesh->host.n_elements();
+    E += (Eg + kReducePer - 1) / kReducePer * kReducePer;
+  }
+  t.E = E;
+  t.G = (int)grp.geoms.size();
+  t.nblk_red = E / kReducePer;
+  size_t total, off[7];
+  ws_layout(t, b->R, &total, off);
+  if (t_out) *t_out = t;
+  return total;
 }
 
 }  // namespace
@@ -230,7 +441,7 @@ using namespace dgd;
 
 extern "C" {
 
-int dgd_version(void) { return 100; }
+int dgd_version(void) { return 200; }
 
 const char* dgd_last_error(void) { return g_last_error.c_str(); }
 
@@ -250,6 +461,9 @@ int dgd_set_option(const char* name, int64_t value) {
       g_opt.stage_waves = (int)value;
     } else if (n == "xcd_remap") {
       g_opt.xcd_remap = value != 0;
+    } else if (n == "stage_grid") {
+      if (value < 0 || value > (1 << 24)) fail(DGD_EINVAL, "stage_grid must be in [0, 2^24]");
+      g_opt.stage_grid = value;
     } else if (n == "mesh_strip") {
       if (value < 0 || value > 16384) fail(DGD_EINVAL, "mesh_strip must be in [0, 16384]");
       g_opt.mesh_strip = (int)value;
@@ -264,7 +478,7 @@ int dgd_mesh_create(double L_um, int32_t n_cells, const double* disks, int32_t n
     if (!out) fail(DGD_EINVAL, "out is NULL");
     *out = nullptr;
     if (!(L_um > 0) || !std::isfinite(L_um)) fail(DGD_EINVAL, "L must be positive and finite");
-    if (n_cells < 1 || n_cells > 16384) fail(DGD_EINVAL, "n_cells must be in [1, 16384]");
+    if (n_cells < 1 || n_cells > kMaxCells) fail(DGD_EINVAL, "n_cells must be in [1, 16383]");
     if (n_disks < 0 || (n_disks > 0 && !disks)) fail(DGD_EINVAL, "bad disk list");
     for (int d = 0; d < n_disks; ++d)
       for (int k = 0; k < 3; ++k)
@@ -274,7 +488,7 @@ int dgd_mesh_create(double L_um, int32_t n_cells, const double* disks, int32_t n
       build_mesh_host(L_um, n_cells, disks, n_disks, g_opt.mesh_strip, m->host);
       const int64_t E = m->host.n_elements();
       if (E > ((int64_t)1 << 31) - 1) fail(DGD_EINVAL, "too many elements");
-      std::vector<int4> pk(std::max<int64_t>(E, 1));
+      std::vector<int4> pk(E);
       for (int64_t e = 0; e < E; ++e) {
         int mask = 0;
         for (int f = 0; f < 3; ++f)
@@ -287,7 +501,6 @@ int dgd_mesh_create(double L_um, int32_t n_cells, const double* disks, int32_t n
       }
       m->packed = std::move(pk);
     } catch (...) {
-      if (m->d_elem) (void)hipFree(m->d_elem);
       delete m;
       throw;
     }
@@ -340,6 +553,7 @@ int dgd_operator_build(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, dou
     if (!(eta > 0) || !std::isfinite(eta)) fail(DGD_EINVAL, "eta must be positive");
     if (precision != DGD_FP64 && precision != DGD_FP32)
       fail(DGD_EINVAL, "precision must be DGD_FP64 or DGD_FP32");
+    if (!std::isfinite(dt_max_ms)) fail(DGD_EINVAL, "dt_max_ms must be finite");
     if (mesh->host.n_elements() == 0) fail(DGD_EINVAL, "mesh has no active element");
     auto* op = new dgd_op();
     try {
@@ -351,9 +565,9 @@ int dgd_operator_build(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, dou
       const RefElem& R = op->ref;
       const int np = R.np;
       // element matrices stay FP64 for both state precisions (FP64 element arithmetic)
-      op->d_S = upload<double>(R.S);
-      op->d_N = upload<double>(R.Nb);
-      op->d_Minv = (double*)upload<double>(R.Minv);
+      op->d_S = upload(R.S);
+      op->d_N = upload(R.Nb);
+      op->d_Minv = (double*)upload(R.Minv);
       const double h = mesh->host.h;
       std::vector<double> Wp(R.W.size()), Mp(R.Mass.size());
       for (int o = 0; o < 2; ++o)
@@ -362,11 +576,11 @@ int dgd_operator_build(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, dou
           for (int j = 0; j < np; ++j) Wp[(o * 6 + a) * np + j] = R.W[(o * 6 + a) * np + j] * s;
         }
       for (size_t k = 0; k < Mp.size(); ++k) Mp[k] = R.Mass[k] * h * h;
-      op->d_W = (double*)upload<double>(Wp);
-      op->d_Mass = (double*)upload<double>(Mp);
+      op->d_W = (double*)upload(Wp);
+      op->d_Mass = (double*)upload(Mp);
       std::vector<double> quad = build_ic_quadrature(R, kQuadN);
       op->nq = kQuadN * kQuadN;
-      op->d_quad = (double*)upload<double>(quad);
+      op->d_quad = (double*)upload(quad);
       const double dt_formula = 0.1 * h * h / (D_um2_per_ms * (p + 1) * (p + 1));
       if (dt_max_ms > 0) {
         op->dt_nom = std::min(dt_formula, dt_max_ms);
@@ -408,9 +622,8 @@ int dgd_workspace_size(const dgd_op* op, int32_t n_points, size_t* bytes) {
   return guarded([&]() -> int {
     if (!op || !bytes) fail(DGD_EINVAL, "NULL argument");
     if (n_points < 1) fail(DGD_EINVAL, "n_points must be >= 1");
-    size_t off[6];
-    int nblk;
-    ws_layout(op, n_points, bytes, off, &nblk);
+    size_t off[7];
+    ws_layout(plain_target(op), n_points, bytes, off);
     return DGD_OK;
   });
 }
@@ -422,10 +635,9 @@ int dgd_operator_apply(dgd_op* op, const void* d_in, void* d_out, int32_t n_rhs,
     if (d_in == d_out) fail(DGD_EINVAL, "input and output must not overlap");
     const int64_t E = op->mesh->host.n_elements();
     const double h = op->mesh->host.h;
-    const Shape sh = stage_shape(E);
     launch_stage(op->precision == DGD_FP64 ? 0 : 1, op->ref.np, d_in, nullptr, d_out,
-                 op->mesh->d_elem, E, op->d_S, op->d_N, 0, 0.0, op->D / (h * h), n_rhs, sh,
-                 (hipStream_t)hip_stream);
+                 op->mesh->d_elem, E, op->d_S, op->d_N, 0, 0.0, op->D / (h * h), n_rhs,
+                 stage_shape(E), (hipStream_t)hip_stream);
     DGD_HIP_CHECK(hipGetLastError());
     return DGD_OK;
   });
@@ -450,70 +662,8 @@ int dgd_run_create(dgd_op* op, const double* points, int32_t n_points, double si
     if (!op || !points) fail(DGD_EINVAL, "NULL argument");
     if (n_points < 1) fail(DGD_EINVAL, "n_points must be >= 1");
     if (!(sigma0_um > 0) || !std::isfinite(sigma0_um)) fail(DGD_EINVAL, "sigma0 must be positive");
-    const MeshHost& mh = op->mesh->host;
-    for (int r = 0; r < n_points; ++r) {
-      const double x = points[2 * r], y = points[2 * r + 1];
-      if (!std::isfinite(x) || !std::isfinite(y) || x < 0 || y < 0 || x >= mh.L || y >= mh.L)
-        fail(DGD_ENOTFREE, "start point " + std::to_string(r) + " lies outside the box");
-      const int i = std::min(mh.N - 1, (int)(x / mh.h)), j = std::min(mh.N - 1, (int)(y / mh.h));
-      if (!mh.active_cell[(size_t)j * mh.N + i])
-        fail(DGD_ENOTFREE, "start point " + std::to_string(r) + " lies in a removed cell");
-    }
-    size_t total, off[6];
-    int nblk;
-    ws_layout(op, n_points, &total, off, &nblk);
-    auto* run = new dgd_run();
-    try {
-      run->op = op;
-      run->R = n_points;
-      run->nblk_red = nblk;
-      run->x0.assign(points, points + 2 * n_points);
-      if (d_ws) {
-        if (ws_bytes < total) fail(DGD_ENOMEM, "workspace smaller than dgd_workspace_size");
-        run->ws = d_ws;
-        run->ws_bytes = ws_bytes;
-      } else {
-        DGD_HIP_CHECK(hipMalloc(&run->ws, total));
-        run->own_ws = true;
-        run->ws_bytes = total;
-      }
-      if (hip_stream) {
-        run->stream = (hipStream_t)hip_stream;
-      } else {
-        DGD_HIP_CHECK(hipStreamCreateWithFlags(&run->stream, hipStreamNonBlocking));
-        run->own_stream = true;
-      }
-      char* base = (char*)run->ws;
-      run->U = base + off[0];
-      run->U1 = base + off[1];
-      run->U2 = base + off[2];
-      run->d_x0 = (double*)(base + off[3]);
-      run->d_part = (double*)(base + off[4]);
-      run->d_mom = (double*)(base + off[5]);
-      DGD_HIP_CHECK(hipMemcpyAsync(run->d_x0, points, (size_t)n_points * 2 * sizeof(double),
-                                   hipMemcpyHostToDevice, run->stream));
-      const int64_t E = op->mesh->host.n_elements();
-      const Shape shr = element_shape(E, kEpwReduce);
-      const Shape sh = stage_shape(E);
-      launch_ic_mass(op->ref.np, op->mesh->d_elem, E, op->d_quad, op->nq, run->d_x0, sigma0_um,
-                     mh.h, kCutoff, n_points, shr, run->d_part, run->stream);
-      launch_reduce(run->d_part, nblk, n_points, run->d_mom, run->stream);
-      launch_ic_project(op->precision == DGD_FP64 ? 0 : 1, op->ref.np, op->mesh->d_elem, E,
-                        op->d_quad, op->nq, op->d_Minv, run->d_x0, run->d_mom, sigma0_um, mh.h,
-                        kCutoff, n_points, sh, run->U, run->stream);
-      DGD_HIP_CHECK(hipGetLastError());
-      std::vector<double> mass((size_t)n_points * 6);
-      DGD_HIP_CHECK(hipMemcpyAsync(mass.data(), run->d_mom, mass.size() * sizeof(double),
-                                   hipMemcpyDeviceToHost, run->stream));
-      DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
-      for (int r = 0; r < n_points; ++r)
-        if (!(mass[r * 6] > 0) || !std::isfinite(mass[r * 6]))
-          fail(DGD_ENOTFREE, "start point " + std::to_string(r) + " has no pulse mass on active cells");
-    } catch (...) {
-      dgd_run_destroy(run);
-      throw;
-    }
-    *out = run;
+    check_points(op->mesh->host, points, n_points);
+    *out = run_create(plain_target(op), points, n_points, sigma0_um, d_ws, ws_bytes, hip_stream);
     return DGD_OK;
   });
 }
@@ -521,21 +671,7 @@ int dgd_run_create(dgd_op* op, const double* points, int32_t n_points, double si
 int dgd_run_advance(dgd_run* run, int64_t n_steps, double dt_ms) {
   return guarded([&]() -> int {
     if (!run) fail(DGD_EINVAL, "run is NULL");
-    if (n_steps < 0) fail(DGD_EINVAL, "n_steps must be >= 0");
-    if (!(dt_ms > 0) || !std::isfinite(dt_ms)) fail(DGD_EINVAL, "dt must be positive");
-    if (n_steps == 0) return DGD_OK;
-    const int64_t G = g_opt.graph_steps;
-    int64_t left = n_steps;
-    if (g_opt.graphs && left >= G) {
-      hipGraphExec_t ex = step_graph(run, G, dt_ms);
-      while (left >= G) {
-        DGD_HIP_CHECK(hipGraphLaunch(ex, run->stream));
-        left -= G;
-      }
-    }
-    run_stage_steps(run, left, dt_ms);
-    DGD_HIP_CHECK(hipGetLastError());
-    run->t_ms += n_steps * dt_ms;
+    run_advance(run, n_steps, dt_ms);
     return DGD_OK;
   });
 }
@@ -543,24 +679,9 @@ int dgd_run_advance(dgd_run* run, int64_t n_steps, double dt_ms) {
 int dgd_run_moments(dgd_run* run, double* moments_out) {
   return guarded([&]() -> int {
     if (!run || !moments_out) fail(DGD_EINVAL, "NULL argument");
-    dgd_op* op = run->op;
-    const int64_t E = op->mesh->host.n_elements();
-    const Shape shr = element_shape(E, kEpwReduce);
-    launch_moments(op->precision == DGD_FP64 ? 0 : 1, op->ref.np, run->U, op->mesh->d_elem, E,
-                   op->d_W, run->d_x0, op->mesh->host.h, run->R, shr, run->d_part, run->stream);
-    launch_reduce(run->d_part, run->nblk_red, run->R, run->d_mom, run->stream);
-    DGD_HIP_CHECK(hipGetLastError());
-    DGD_HIP_CHECK(hipMemcpyAsync(moments_out, run->d_mom, (size_t)run->R * 6 * sizeof(double),
-                                 hipMemcpyDeviceToHost, run->stream));
-    DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
-    const double tol = op->precision == DGD_FP64 ? 1e-9 : 1e-3;
-    for (int r = 0; r < run->R; ++r) {
-      for (int c = 0; c < 6; ++c)
-        if (!std::isfinite(moments_out[r * 6 + c]))
-          fail(DGD_EUNSTABLE, "non-finite moment for start point " + std::to_string(r));
-      if (std::fabs(moments_out[r * 6] - 1.0) > tol)
-        fail(DGD_EUNSTABLE, "mass drift beyond tolerance for start point " + std::to_string(r));
-    }
+    std::string why;
+    const int rc = run_moments(run, moments_out, &why);
+    if (rc) fail(rc, why);
     return DGD_OK;
   });
 }
@@ -568,8 +689,7 @@ int dgd_run_moments(dgd_run* run, double* moments_out) {
 int dgd_run_get_state(dgd_run* run, void* host_out) {
   return guarded([&]() -> int {
     if (!run || !host_out) fail(DGD_EINVAL, "NULL argument");
-    const size_t n = (size_t)run->op->mesh->host.n_elements() * run->op->ref.np * run->R *
-                     state_bytes(run->op->precision);
+    const size_t n = (size_t)run->t.E * run->t.np * run->R * state_bytes(run->t.prec);
     DGD_HIP_CHECK(hipMemcpyAsync(host_out, run->U, n, hipMemcpyDeviceToHost, run->stream));
     DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
     return DGD_OK;
@@ -579,64 +699,252 @@ int dgd_run_get_state(dgd_run* run, void* host_out) {
 int dgd_run_set_state(dgd_run* run, const void* host_in) {
   return guarded([&]() -> int {
     if (!run || !host_in) fail(DGD_EINVAL, "NULL argument");
-    const size_t n = (size_t)run->op->mesh->host.n_elements() * run->op->ref.np * run->R *
-                     state_bytes(run->op->precision);
+    const size_t n = (size_t)run->t.E * run->t.np * run->R * state_bytes(run->t.prec);
     DGD_HIP_CHECK(hipMemcpyAsync(run->U, host_in, n, hipMemcpyHostToDevice, run->stream));
     DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
     return DGD_OK;
   });
 }
 
-void dgd_run_destroy(dgd_run* run) {
-  if (!run) return;
-  if (run->stream) (void)hipStreamSynchronize(run->stream);
-  for (auto& kv : run->graphs) (void)hipGraphExecDestroy(kv.second);
-  if (run->own_ws) (void)hipFree(run->ws);
-  if (run->own_stream) (void)hipStreamDestroy(run->stream);
-  delete run;
-}
+void dgd_run_destroy(dgd_run* run) { run_destroy(run); }
 
 int dgd_eap_solve(dgd_op* op, const double* points, int32_t n_points, double sigma0_um,
                   const double* deltas_ms, int32_t n_deltas, double* sigma_out, double* moments_out,
                   void* d_ws, size_t ws_bytes, void* hip_stream) {
   dgd_run* run = nullptr;
+  std::vector<std::pair<int64_t, double>> sched;
   int rc = guarded([&]() -> int {
     if (!op || !deltas_ms || !sigma_out) fail(DGD_EINVAL, "NULL argument");
     if (n_deltas < 1) fail(DGD_EINVAL, "n_deltas must be >= 1");
-    double prev = 0;
-    for (int k = 0; k < n_deltas; ++k) {
-      if (!std::isfinite(deltas_ms[k]) || !(deltas_ms[k] > prev))
-        fail(DGD_EINVAL, "Delta list must be finite, positive and strictly increasing");
-      prev = deltas_ms[k];
-    }
+    sched = schedule(deltas_ms, n_deltas, op->dt_nom);
     return DGD_OK;
   });
   if (rc) return rc;
   rc = dgd_run_create(op, points, n_points, sigma0_um, d_ws, ws_bytes, hip_stream, &run);
   if (rc) return rc;
-  std::vector<double> mom((size_t)n_points * 6);
-  double prev = 0;
-  for (int k = 0; k < n_deltas && rc == 0; ++k) {
-    const double span = deltas_ms[k] - prev;
-    int64_t n = (int64_t)std::ceil(span / op->dt_nom - 1e-9);
-    if (n < 1) n = 1;
-    const double dt = span / (double)n;
-    rc = dgd_run_advance(run, n, dt);
-    if (rc) break;
-    const int mrc = dgd_run_moments(run, mom.data());
-    for (int r = 0; r < n_points; ++r) {
-      const double* m = &mom[(size_t)r * 6];
-      double* s = &sigma_out[((size_t)r * n_deltas + k) * 3];
-      s[0] = m[3] / m[0];
-      s[1] = m[4] / m[0];
-      s[2] = m[5] / m[0];
-      if (moments_out) std::memcpy(&moments_out[((size_t)r * n_deltas + k) * 6], m, 6 * sizeof(double));
+  rc = guarded([&]() -> int {
+    std::vector<double> mom((size_t)n_points * 6);
+    int status = DGD_OK;
+    std::string why;
+    for (int k = 0; k < n_deltas; ++k) {
+      run_advance(run, sched[k].first, sched[k].second);
+      const int mrc = run_moments(run, mom.data(), &why);
+      for (int r = 0; r < n_points; ++r) {
+        const double* m = &mom[(size_t)r * 6];
+        double* s = &sigma_out[((size_t)r * n_deltas + k) * 3];
+        s[0] = m[3] / m[0];
+        s[1] = m[4] / m[0];
+        s[2] = m[5] / m[0];
+        if (moments_out)
+          std::memcpy(&moments_out[((size_t)r * n_deltas + k) * 6], m, 6 * sizeof(double));
+      }
+      if (mrc) {
+        status = mrc;
+        break;
+      }
     }
-    if (mrc) rc = mrc;
-    prev = deltas_ms[k];
-  }
-  // keep the message of the first failure: destroy does not touch it
+    if (status) fail(status, why);
+    return DGD_OK;
+  });
   dgd_run_destroy(run);
+  return rc;
+}
+
+// ---------------------------------------------------------------- batch ----
+
+int dgd_batch_workspace_size(dgd_op* const* ops, int32_t n_geoms, int32_t n_points, size_t* bytes) {
+  return guarded([&]() -> int {
+    if (!ops || !bytes || n_geoms < 1 || n_points < 1) fail(DGD_EINVAL, "bad argument");
+    dgd_batch b;
+    b.G = n_geoms;
+    b.R = n_points;
+    b.ops.assign(ops, ops + n_geoms);
+    for (auto* o : b.ops)
+      if (!o) fail(DGD_EINVAL, "NULL operator");
+    batch_plan(&b);
+    size_t total = 0;
+    for (auto& g : b.groups) total += align256(batch_group_bytes(g, &b, nullptr));
+    *bytes = total;
+    return DGD_OK;
+  });
+}
+
+int dgd_batch_create(dgd_op* const* ops, int32_t n_geoms, const double* points, int32_t n_points,
+                     double sigma0_um, void* d_ws, size_t ws_bytes, void* hip_stream,
+                     dgd_batch** out) {
+  return guarded([&]() -> int {
+    if (!out) fail(DGD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ops || !points || n_geoms < 1 || n_points < 1) fail(DGD_EINVAL, "bad argument");
+    if (!(sigma0_um > 0) || !std::isfinite(sigma0_um)) fail(DGD_EINVAL, "sigma0 must be positive");
+    for (int g = 0; g < n_geoms; ++g) {
+      if (!ops[g]) fail(DGD_EINVAL, "NULL operator");
+      const dgd_op* a = ops[g];
+      const dgd_op* z = ops[0];
+      if (a->mesh->host.h != z->mesh->host.h || a->D != z->D || a->ref.eta != z->ref.eta ||
+          a->precision != z->precision)
+        fail(DGD_EINVAL, "batched operators must share h, D, eta and precision");
+      check_points(a->mesh->host, points + (size_t)g * n_points * 2, n_points, g * n_points);
+    }
+    auto* b = new dgd_batch();
+    try {
+      b->G = n_geoms;
+      b->R = n_points;
+      b->ops.assign(ops, ops + n_geoms);
+      batch_plan(b);
+      size_t used = 0;
+      for (auto& grp : b->groups) {
+        RunTarget t;
+        const size_t need = batch_group_bytes(grp, b, &t);
+        // concatenated element table, block -> geometry map, block ranges
+        std::vector<int4> elem;
+        elem.reserve(t.E);
+        std::vector<int> blk_geom, blk_start;
+        grp.dt = 1e300;
+        for (int k = 0; k < (int)grp.geoms.size(); ++k) {
+          const dgd_op* op = b->ops[grp.geoms[k]];
+          const int64_t off = (int64_t)elem.size();
+          blk_start.push_back((int)(off / kReducePer));
+          for (const int4& e : op->mesh->packed) {
+            int4 c = e;
+            if (c.x >= 0) c.x += (int)off;
+            if (c.y >= 0) c.y += (int)off;
+            if (c.z >= 0) c.z += (int)off;
+            elem.push_back(c);
+          }
+          int4 pad;
+          pad.x = pad.y = pad.z = -1;
+          pad.w = (int)(((uint32_t)kPadCell << 4) | ((uint32_t)kPadCell << 18));
+          while (elem.size() % kReducePer) elem.push_back(pad);
+          while ((int64_t)blk_geom.size() < (int64_t)elem.size() / kReducePer) blk_geom.push_back(k);
+          grp.dt = std::min(grp.dt, op->dt_nom);
+          grp.dof += op->mesh->host.n_elements() * op->ref.np;
+        }
+        blk_start.push_back((int)(elem.size() / kReducePer));
+        if ((int64_t)elem.size() != t.E) fail(DGD_EINVAL, "internal: batch size mismatch");
+        grp.E = t.E;
+        grp.d_elem = (int4*)upload(elem);
+        grp.d_blk_geom = (int*)upload(blk_geom);
+        grp.d_blk_start = (int*)upload(blk_start);
+        t.elem = grp.d_elem;
+        t.blk_geom = grp.d_blk_geom;
+        t.blk_start = grp.d_blk_start;
+        std::vector<double> x0;
+        for (int g : grp.geoms)
+          x0.insert(x0.end(), points + (size_t)g * n_points * 2,
+                    points + (size_t)(g + 1) * n_points * 2);
+        void* ws = nullptr;
+        if (d_ws) {
+          if (used + need > ws_bytes)
+            fail(DGD_ENOMEM, "workspace smaller than dgd_batch_workspace_size");
+          ws = (char*)d_ws + used;
+          used += align256(need);
+        }
+        grp.run = run_create(t, x0.data(), n_points, sigma0_um, ws, ws ? need : 0, hip_stream);
+      }
+    } catch (...) {
+      batch_destroy(b);
+      throw;
+    }
+    *out = b;
+    return DGD_OK;
+  });
+}
+
+int dgd_batch_groups(const dgd_batch* b, int32_t* n_groups, int32_t* group_p, int32_t* group_size,
+                     double* group_dt, int64_t* group_dof) {
+  return guarded([&]() -> int {
+    if (!b) fail(DGD_EINVAL, "batch is NULL");
+    if (n_groups) *n_groups = (int32_t)b->groups.size();
+    for (size_t k = 0; k < b->groups.size(); ++k) {
+      if (group_p) group_p[k] = b->groups[k].p;
+      if (group_size) group_size[k] = (int32_t)b->groups[k].geoms.size();
+      if (group_dt) group_dt[k] = b->groups[k].dt;
+      if (group_dof) group_dof[k] = b->groups[k].dof;
+    }
+    return DGD_OK;
+  });
+}
+
+int dgd_batch_advance(dgd_batch* b, int32_t group, int64_t n_steps, double dt_ms) {
+  return guarded([&]() -> int {
+    if (!b || group < 0 || group >= (int)b->groups.size()) fail(DGD_EINVAL, "bad batch or group");
+    run_advance(b->groups[group].run, n_steps, dt_ms);
+    return DGD_OK;
+  });
+}
+
+int dgd_batch_moments(dgd_batch* b, double* moments_out) {
+  return guarded([&]() -> int {
+    if (!b || !moments_out) fail(DGD_EINVAL, "NULL argument");
+    int status = DGD_OK;
+    std::string why;
+    for (auto& grp : b->groups) {
+      std::vector<double> m((size_t)grp.geoms.size() * b->R * 6);
+      std::string w;
+      const int rc = run_moments(grp.run, m.data(), &w);
+      if (rc && !status) {
+        status = rc;
+        why = w;
+      }
+      for (size_t k = 0; k < grp.geoms.size(); ++k)
+        std::memcpy(moments_out + (size_t)grp.geoms[k] * b->R * 6, &m[k * b->R * 6],
+                    (size_t)b->R * 6 * sizeof(double));
+    }
+    if (status) fail(status, why);
+    return DGD_OK;
+  });
+}
+
+void dgd_batch_destroy(dgd_batch* b) { batch_destroy(b); }
+
+int dgd_eap_solve_batch(dgd_op* const* ops, int32_t n_geoms, const double* points,
+                        int32_t n_points, double sigma0_um, const double* deltas_ms,
+                        int32_t n_deltas, double* sigma_out, double* moments_out, void* d_ws,
+                        size_t ws_bytes, void* hip_stream) {
+  dgd_batch* b = nullptr;
+  int rc = guarded([&]() -> int {
+    if (!deltas_ms || !sigma_out || n_deltas < 1) fail(DGD_EINVAL, "bad Delta list or output");
+    schedule(deltas_ms, n_deltas, 1.0);  // validates the list
+    return DGD_OK;
+  });
+  if (rc) return rc;
+  rc = dgd_batch_create(ops, n_geoms, points, n_points, sigma0_um, d_ws, ws_bytes, hip_stream, &b);
+  if (rc) return rc;
+  rc = guarded([&]() -> int {
+    const int R = n_points;
+    int status = DGD_OK;
+    std::string why;
+    for (auto& grp : b->groups) {
+      const auto sched = schedule(deltas_ms, n_deltas, grp.dt);
+      std::vector<double> m((size_t)grp.geoms.size() * R * 6);
+      for (int k = 0; k < n_deltas; ++k) {
+        run_advance(grp.run, sched[k].first, sched[k].second);
+        std::string w;
+        const int mrc = run_moments(grp.run, m.data(), &w);
+        for (size_t q = 0; q < grp.geoms.size(); ++q) {
+          const int g = grp.geoms[q];
+          for (int r = 0; r < R; ++r) {
+            const double* mm = &m[(q * R + r) * 6];
+            double* s = &sigma_out[(((size_t)g * R + r) * n_deltas + k) * 3];
+            s[0] = mm[3] / mm[0];
+            s[1] = mm[4] / mm[0];
+            s[2] = mm[5] / mm[0];
+            if (moments_out)
+              std::memcpy(&moments_out[(((size_t)g * R + r) * n_deltas + k) * 6], mm,
+                          6 * sizeof(double));
+          }
+        }
+        if (mrc && !status) {
+          status = mrc;
+          why = w;
+        }
+      }
+    }
+    if (status) fail(status, why);
+    return DGD_OK;
+  });
+  dgd_batch_destroy(b);
   return rc;
 }
 

@@ -84,8 +84,31 @@ struct dgd_op {
   int nq = 0;
 };
 
+namespace dgd {
+
+// What a run advances: an element table (one mesh, or several meshes
+// concatenated as disconnected components) and the element operator.
+struct RunTarget {
+  const int4* elem = nullptr;
+  int64_t E = 0;
+  int np = 0, prec = 0;
+  const void* S = nullptr;       // FP64 [2][8][np][np]
+  const void* N = nullptr;       // FP64 [2][3][np][np]
+  double D = 0, h = 0;
+  const double* W = nullptr;     // physical moment weights [2][6][np]
+  const double* Minv = nullptr;  // reference inverse mass [2][np][np]
+  const double* quad = nullptr;  // initial-data quadrature
+  int nq = 0;
+  int G = 1;                     // geometries
+  const int* blk_geom = nullptr; // device [nblk_red] geometry of each reduction block (G > 1)
+  const int* blk_start = nullptr;// device [G + 1] reduction-block range of each geometry (G > 1)
+  int64_t nblk_red = 0;          // reduction blocks covering the elements
+};
+
+}  // namespace dgd
+
 struct dgd_run {
-  dgd_op* op = nullptr;
+  dgd::RunTarget t;
   int R = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -95,12 +118,31 @@ struct dgd_run {
   void* U = nullptr;   // state u^n
   void* U1 = nullptr;  // stage 1
   void* U2 = nullptr;  // stage 2
-  double* d_x0 = nullptr;     // [R][2]
-  double* d_part = nullptr;   // [nblk][R][6] partial sums
-  double* d_mom = nullptr;    // [R][6]
-  int nblk_red = 0;
+  double* d_x0 = nullptr;     // [G][R][2]
+  double* d_part = nullptr;   // [nblk_red][R][6] partial sums
+  double* d_mom = nullptr;    // [G][R][6]
+  int* d_blk_start = nullptr; // [G + 1] (plain runs: {0, nblk_red})
   std::vector<double> x0;
   double t_ms = 0;
   // captured step graphs keyed by (dt bits, steps)
   std::map<std::pair<uint64_t, int64_t>, hipGraphExec_t> graphs;
+};
+
+// Several geometries solved together, grouped by polynomial degree: each
+// group is one run over the concatenated element tables of its geometries.
+struct dgd_batch {
+  int G = 0, R = 0;
+  std::vector<dgd_op*> ops;
+  struct Group {
+    int p = 0;
+    std::vector<int> geoms;        // batch indices of the member geometries
+    int4* d_elem = nullptr;
+    int* d_blk_geom = nullptr;
+    int* d_blk_start = nullptr;
+    int64_t E = 0;                 // padded elements
+    int64_t dof = 0;               // active DoF per right-hand side
+    double dt = 0;                 // min of the members' nominal steps
+    dgd_run* run = nullptr;
+  };
+  std::vector<Group> groups;
 };

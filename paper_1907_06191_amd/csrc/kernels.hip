@@ -3,11 +3,16 @@
 // Layout: the state of R solves is u[e][j][r] (element, node, right-hand
 // side), r fastest, so that a wave's 64 lanes read 64 consecutive values of
 // one node of one element: every state access is a fully coalesced
-// 256-byte (FP32) or 512-byte (FP64) line.  A wave owns one element at a
+// 256-byte (FP32) or 512-byte (FP64) row.  A wave owns one element at a
 // time, so the element's orientation, face mask and neighbours are
 // wave-uniform: they come in through one scalar load, and the element
 // matrices (shared by all elements of one orientation and mask) are read
 // through the scalar cache and used as SGPR operands of the VALU FMAs.
+//
+// Several geometries can share one launch: their element tables are
+// concatenated (disconnected components of one mesh), and the reduction
+// kernels read the geometry of each block from `blk_geom` to pick the start
+// points of that geometry.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -18,22 +23,43 @@ namespace dgd {
 namespace {
 
 constexpr int WAVE = 64;
+// Cell index of the padding elements that align each geometry of a batch to
+// whole reduction blocks (meshes have at most 16383 cells per side).
+constexpr int kPadCell = 0x3fff;
 
-__device__ inline int64_t logical_block(int64_t nblocks) {
-  // Workgroups are dispatched round-robin over the 8 XCDs (blockIdx.x mod 8).
-  // Give XCD x the contiguous logical range [x * per, (x + 1) * per), walked
-  // in dispatch order, so neighbouring rows of cells -- the vertical face
-  // neighbours -- are read while still in that XCD's L2.  A negative
-  // nblocks asks for the plain identity mapping.
-  const int64_t b = blockIdx.x;
-  if (nblocks < 0) return b;
-  const int64_t per = (int64_t)gridDim.x / 8;
-  return (b % 8) * per + b / 8;
+// Logical blocks walked by this workgroup.  Workgroups are dispatched
+// round-robin over the 8 XCDs (blockIdx.x mod 8).  With `remap`, XCD x owns
+// the contiguous logical range [x * per, (x + 1) * per) and its workgroups
+// stride through it in dispatch order, so rows of cells that are face
+// neighbours are read while still in that XCD's L2.  A grid smaller than the
+// number of logical blocks makes the kernel persistent (each workgroup loops).
+struct BlockIter {
+  int64_t first, stride, end;
+};
+
+__device__ inline BlockIter block_iter(int64_t nblocks, int remap) {
+  BlockIter it;
+  const int64_t G = gridDim.x;
+  if (remap) {
+    const int64_t per = (nblocks + 7) / 8;
+    const int64_t x = blockIdx.x % 8;
+    it.first = x * per + blockIdx.x / 8;
+    it.stride = G / 8;
+    const int64_t hi = (x + 1) * per;
+    it.end = hi < nblocks ? hi : nblocks;
+  } else {
+    it.first = blockIdx.x;
+    it.stride = G;
+    it.end = nblocks;
+  }
+  return it;
 }
 
 // mode 0 (operator apply):  out = cg * L(us)
 // mode 1 (SSP-RK3 stage):    out = base + cb * (us - base) + cg * L(us),
 //                            base = ub when given, else us.
+// L(us)_K = S_{o,mask}(us_K - c) + sum_{f in mask} N_{o,f}(us_f - c),
+// c = us_K[node 0] (exact zero on constants whatever the rounding of S, N).
 // Writing the stage as a correction of `base` keeps the weight of the base
 // state exactly 1 (in FP32, fl(1/3) + fl(2/3) = 1 + 3e-8, which the textbook
 // form 1/3 u + 2/3 u2 would turn into a mass growth of 3e-8 per step).
@@ -49,9 +75,8 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
                                                const int4* __restrict__ elem, int64_t E,
                                                const double* __restrict__ S,
                                                const double* __restrict__ Nm, int mode, double cb,
-                                               double cg, int R, int epw, int64_t nblocks) {
-  const int64_t b = logical_block(nblocks);
-  if (b >= (nblocks < 0 ? -nblocks : nblocks)) return;
+                                               double cg, int R, int epw, int64_t nblocks,
+                                               int remap) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   // right-hand sides: 64 per wave, chunk blockIdx.y; lanes past R load a
@@ -59,151 +84,178 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
   const int r_raw = blockIdx.y * WAVE + lane;
   const bool live = r_raw < R;
   const int r = live ? r_raw : R - 1;
-  const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
-  const int64_t e1 = e0 + epw < E ? e0 + epw : E;
   const bool use_base = ub != nullptr;
-  for (int64_t e = e0; e < e1; ++e) {
-    const int4 m = elem[e];
-    const int o = m.w & 1;
-    const int mask = (m.w >> 1) & 7;
-    const int64_t self = (e * NP) * (int64_t)R + r;
-    // issue every load of the element first: own nodes, the three
-    // neighbours (a missing neighbour reads the element itself, a cache
-    // hit, and its product is skipped below), the RK base state
-    const int64_t n0 = (m.x >= 0 ? (int64_t)m.x * NP * R + r : self);
-    const int64_t n1 = (m.y >= 0 ? (int64_t)m.y * NP * R + r : self);
-    const int64_t n2 = (m.z >= 0 ? (int64_t)m.z * NP * R + r : self);
-    TS su[NP], s0[NP], s1[NP], s2[NP], sb[NP];
+  const BlockIter it = block_iter(nblocks, remap);
+  for (int64_t b = it.first; b < it.end; b += it.stride) {
+    const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
+    const int64_t e1 = e0 + epw < E ? e0 + epw : E;
+    for (int64_t e = e0; e < e1; ++e) {
+      const int4 m = elem[e];
+      const int o = m.w & 1;
+      const int mask = (m.w >> 1) & 7;
+      const int64_t self = (e * NP) * (int64_t)R + r;
+      // issue every load of the element first: own nodes, the three
+      // neighbours (a missing neighbour reads the element itself, a cache
+      // hit, and its product is skipped below), the RK base state
+      const int64_t n0 = (m.x >= 0 ? (int64_t)m.x * NP * R + r : self);
+      const int64_t n1 = (m.y >= 0 ? (int64_t)m.y * NP * R + r : self);
+      const int64_t n2 = (m.z >= 0 ? (int64_t)m.z * NP * R + r : self);
+      TS su[NP], s0[NP], s1[NP], s2[NP], sb[NP];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-      su[j] = us[self + (int64_t)j * R];
-      s0[j] = us[n0 + (int64_t)j * R];
-      s1[j] = us[n1 + (int64_t)j * R];
-      s2[j] = us[n2 + (int64_t)j * R];
-    }
-    if (use_base) {
-#pragma unroll
-      for (int j = 0; j < NP; ++j) sb[j] = ub[self + (int64_t)j * R];
-    }
-    const double c = (double)su[0];
-    double acc[NP];
-    {
-      const double* Se = S + (o * 8 + mask) * NP * NP;
-      double d[NP];
-#pragma unroll
-      for (int j = 0; j < NP; ++j) d[j] = (double)su[j] - c;
-#pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        double a = 0.0;
-#pragma unroll
-        for (int j = 0; j < NP; ++j) a = fma(Se[i * NP + j], d[j], a);
-        acc[i] = a;
+      for (int j = 0; j < NP; ++j) {
+        su[j] = us[self + (int64_t)j * R];
+        s0[j] = us[n0 + (int64_t)j * R];
+        s1[j] = us[n1 + (int64_t)j * R];
+        s2[j] = us[n2 + (int64_t)j * R];
       }
-    }
-#define DGD_FACE(F, SV)                                                        \
-    if (mask & (1 << F)) {                                                     \
-      const double* Nf = Nm + (o * 3 + F) * NP * NP;                           \
-      double dn[NP];                                                           \
-      _Pragma("unroll") for (int j = 0; j < NP; ++j) dn[j] = (double)SV[j] - c; \
-      _Pragma("unroll") for (int i = 0; i < NP; ++i) {                         \
-        double a = acc[i];                                                     \
-        _Pragma("unroll") for (int j = 0; j < NP; ++j) a = fma(Nf[i * NP + j], dn[j], a); \
-        acc[i] = a;                                                            \
-      }                                                                        \
-    }
-    DGD_FACE(0, s0)
-    DGD_FACE(1, s1)
-    DGD_FACE(2, s2)
+      if (use_base) {
+#pragma unroll
+        for (int j = 0; j < NP; ++j) sb[j] = ub[self + (int64_t)j * R];
+      }
+      const double c = (double)su[0];
+      double acc[NP];
+      {
+        const double* Se = S + (o * 8 + mask) * NP * NP;
+        double d[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) d[j] = (double)su[j] - c;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          double a = 0.0;
+#pragma unroll
+          for (int j = 0; j < NP; ++j) a = fma(Se[i * NP + j], d[j], a);
+          acc[i] = a;
+        }
+      }
+#define DGD_FACE(F, SV)                                                                   \
+      if (mask & (1 << F)) {                                                              \
+        const double* Nf = Nm + (o * 3 + F) * NP * NP;                                    \
+        double dn[NP];                                                                    \
+        _Pragma("unroll") for (int j = 0; j < NP; ++j) dn[j] = (double)SV[j] - c;         \
+        _Pragma("unroll") for (int i = 0; i < NP; ++i) {                                  \
+          double a = acc[i];                                                              \
+          _Pragma("unroll") for (int j = 0; j < NP; ++j) a = fma(Nf[i * NP + j], dn[j], a); \
+          acc[i] = a;                                                                     \
+        }                                                                                 \
+      }
+      DGD_FACE(0, s0)
+      DGD_FACE(1, s1)
+      DGD_FACE(2, s2)
 #undef DGD_FACE
-    if (!live) continue;
-    if (mode == 0) {
+      if (!live) continue;
+      if (mode == 0) {
 #pragma unroll
-      for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)(cg * acc[i]);
-    } else if (use_base) {
+        for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)(cg * acc[i]);
+      } else if (use_base) {
 #pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        const double b0 = (double)sb[i];
-        out[self + (int64_t)i * R] = (TS)(b0 + cb * ((double)su[i] - b0) + cg * acc[i]);
+        for (int i = 0; i < NP; ++i) {
+          const double b0 = (double)sb[i];
+          out[self + (int64_t)i * R] = (TS)(b0 + cb * ((double)su[i] - b0) + cg * acc[i]);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+          out[self + (int64_t)i * R] = (TS)((double)su[i] + cg * acc[i]);
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)((double)su[i] + cg * acc[i]);
     }
   }
 }
 
-// Per-block partial moments: part[b][r][0..5] with element-local offsets
-// d = c_K - x0 in FP64 (c_K the cell centre from integer indices).
+// Reduction kernels share one shape: 4 waves per workgroup, each wave walks
+// `epw` consecutive elements, lanes on right-hand sides; per-block partials
+// part[b][r][6] are summed later in a fixed order (deterministic).
+
+// Partial moments with element-local offsets d = c_K - x0 in FP64 (c_K the
+// cell centre from integer indices).  x0 is [G][R][2].
 template <typename T, int NP>
 __global__ void __launch_bounds__(256) k_moments(const T* __restrict__ u,
                                                  const int4* __restrict__ elem, int64_t E,
                                                  const double* __restrict__ W,
-                                                 const double* __restrict__ x0, double h, int R,
-                                                 int epw, int64_t nblocks, double* __restrict__ part) {
+                                                 const double* __restrict__ x0,
+                                                 const int* __restrict__ blk_geom, double h, int R,
+                                                 int epw, int64_t nblocks,
+                                                 double* __restrict__ part) {
   __shared__ double red[4][WAVE][6];
-  const int64_t b = logical_block(nblocks);
-  if (b >= (nblocks < 0 ? -nblocks : nblocks)) return;
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
-  const int64_t e1 = e0 + epw < E ? e0 + epw : E;
-  for (int r0 = 0; r0 < R; r0 += WAVE) {
-    const int r = r0 + lane;
-    double a0 = 0, ax = 0, ay = 0, axx = 0, axy = 0, ayy = 0;
-    if (r < R) {
-      const double px = x0[2 * r], py = x0[2 * r + 1];
-      for (int64_t e = e0; e < e1; ++e) {
-        const int4 m = elem[e];
-        const int o = m.w & 1;
-        const int ci = (m.w >> 4) & 0x3fff;
-        const int cj = (m.w >> 18) & 0x3fff;
-        const double* Wo = W + o * 6 * NP;
-        double i0 = 0, ix = 0, iy = 0, ixx = 0, ixy = 0, iyy = 0;
-        const int64_t base = (e * NP) * (int64_t)R + r;
+  const BlockIter it = block_iter(nblocks, 1);
+  for (int64_t b = it.first; b < it.end; b += it.stride) {
+    const int g = blk_geom ? blk_geom[b] : 0;
+    const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
+    const int64_t e1 = e0 + epw < E ? e0 + epw : E;
+    for (int r0 = 0; r0 < R; r0 += WAVE) {
+      const int r = r0 + lane;
+      double a0 = 0, ax = 0, ay = 0, axx = 0, axy = 0, ayy = 0;
+      if (r < R) {
+        const double px = x0[((int64_t)g * R + r) * 2], py = x0[((int64_t)g * R + r) * 2 + 1];
+        for (int64_t e = e0; e < e1; ++e) {
+          const int4 m = elem[e];
+          const int o = m.w & 1;
+          const int ci = (m.w >> 4) & 0x3fff;
+          const int cj = (m.w >> 18) & 0x3fff;
+          const double* Wo = W + o * 6 * NP;
+          double i0 = 0, ix = 0, iy = 0, ixx = 0, ixy = 0, iyy = 0;
+          const int64_t base = (e * NP) * (int64_t)R + r;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) {
-          const double v = (double)u[base + (int64_t)j * R];
-          i0 += Wo[0 * NP + j] * v;
-          ix += Wo[1 * NP + j] * v;
-          iy += Wo[2 * NP + j] * v;
-          ixx += Wo[3 * NP + j] * v;
-          ixy += Wo[4 * NP + j] * v;
-          iyy += Wo[5 * NP + j] * v;
+          for (int j = 0; j < NP; ++j) {
+            const double v = (double)u[base + (int64_t)j * R];
+            i0 += Wo[0 * NP + j] * v;
+            ix += Wo[1 * NP + j] * v;
+            iy += Wo[2 * NP + j] * v;
+            ixx += Wo[3 * NP + j] * v;
+            ixy += Wo[4 * NP + j] * v;
+            iyy += Wo[5 * NP + j] * v;
+          }
+          const double dx = (ci + 0.5) * h - px;
+          const double dy = (cj + 0.5) * h - py;
+          a0 += i0;
+          ax += ix + dx * i0;
+          ay += iy + dy * i0;
+          axx += ixx + 2.0 * dx * ix + dx * dx * i0;
+          axy += ixy + dx * iy + dy * ix + dx * dy * i0;
+          ayy += iyy + 2.0 * dy * iy + dy * dy * i0;
         }
-        const double dx = (ci + 0.5) * h - px;
-        const double dy = (cj + 0.5) * h - py;
-        a0 += i0;
-        ax += ix + dx * i0;
-        ay += iy + dy * i0;
-        axx += ixx + 2.0 * dx * ix + dx * dx * i0;
-        axy += ixy + dx * iy + dy * ix + dx * dy * i0;
-        ayy += iyy + 2.0 * dy * iy + dy * dy * i0;
       }
-    }
-    red[w][lane][0] = a0;
-    red[w][lane][1] = ax;
-    red[w][lane][2] = ay;
-    red[w][lane][3] = axx;
-    red[w][lane][4] = axy;
-    red[w][lane][5] = ayy;
-    __syncthreads();
-    if (w == 0 && r < R) {
-      for (int c = 0; c < 6; ++c) {
-        double s = red[0][lane][c];
-        for (int k = 1; k < (int)(blockDim.x / WAVE); ++k) s += red[k][lane][c];
-        part[(b * R + r) * 6 + c] = s;
+      red[w][lane][0] = a0;
+      red[w][lane][1] = ax;
+      red[w][lane][2] = ay;
+      red[w][lane][3] = axx;
+      red[w][lane][4] = axy;
+      red[w][lane][5] = ayy;
+      __syncthreads();
+      if (w == 0 && r < R) {
+        for (int c = 0; c < 6; ++c) {
+          double s = red[0][lane][c];
+          for (int k = 1; k < (int)(blockDim.x / WAVE); ++k) s += red[k][lane][c];
+          part[(b * R + r) * 6 + c] = s;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
-__global__ void k_reduce(const double* __restrict__ part, int nblk, int R, double* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= R * 6) return;
+// out[g][r][c] = sum of part[b][r][c] over the blocks b of geometry g.  One
+// 64-lane workgroup per output value: each lane sums a strided subset of the
+// blocks in order, then a fixed-order tree over the 64 lanes.
+__global__ void __launch_bounds__(64) k_reduce_seg(const double* __restrict__ part,
+                                                   const int* __restrict__ blk_start, int G, int R,
+                                                   double* __restrict__ out) {
+  const int t = blockIdx.x;            // (g * R + r) * 6 + c
+  if (t >= G * R * 6) return;
+  const int g = t / (R * 6);
+  const int rc = t % (R * 6);
+  const int b0 = blk_start[g], b1 = blk_start[g + 1];
   double s = 0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * R * 6 + t];
-  out[t] = s;
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += 64) s += part[(int64_t)b * R * 6 + rc];
+  __shared__ double sh[64];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 32; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[t] = sh[0];
 }
 
 __device__ inline bool near_cell(int ci, int cj, double h, double px, double py, double lim) {
@@ -219,103 +271,112 @@ __device__ inline bool near_cell(int ci, int cj, double h, double px, double py,
 template <int NP>
 __global__ void __launch_bounds__(256) k_ic_mass(const int4* __restrict__ elem, int64_t E,
                                                  const double* __restrict__ quad, int nq,
-                                                 const double* __restrict__ x0, double sigma0,
+                                                 const double* __restrict__ x0,
+                                                 const int* __restrict__ blk_geom, double sigma0,
                                                  double h, double cutoff, int R, int epw,
                                                  int64_t nblocks, double* __restrict__ part) {
   __shared__ double red[4][WAVE];
-  const int64_t b = logical_block(nblocks);
-  if (b >= (nblocks < 0 ? -nblocks : nblocks)) return;
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
-  const int64_t e1 = e0 + epw < E ? e0 + epw : E;
   const double inv2s2 = 1.0 / (2.0 * sigma0 * sigma0);
   const double lim = cutoff * sigma0;
-  for (int r0 = 0; r0 < R; r0 += WAVE) {
-    const int r = r0 + lane;
-    double acc = 0;
-    if (r < R) {
-      const double px = x0[2 * r], py = x0[2 * r + 1];
-      for (int64_t e = e0; e < e1; ++e) {
-        const int4 m = elem[e];
-        const int o = m.w & 1;
-        const int ci = (m.w >> 4) & 0x3fff;
-        const int cj = (m.w >> 18) & 0x3fff;
-        if (!near_cell(ci, cj, h, px, py, lim)) continue;
-        const double* Q = quad + (int64_t)o * nq * (3 + NP);
-        double s = 0;
-        for (int q = 0; q < nq; ++q) {
-          const double X = (ci + Q[q * (3 + NP)]) * h - px;
-          const double Y = (cj + Q[q * (3 + NP) + 1]) * h - py;
-          s += Q[q * (3 + NP) + 2] * exp(-(X * X + Y * Y) * inv2s2);
+  const BlockIter it = block_iter(nblocks, 1);
+  for (int64_t b = it.first; b < it.end; b += it.stride) {
+    const int g = blk_geom ? blk_geom[b] : 0;
+    const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
+    const int64_t e1 = e0 + epw < E ? e0 + epw : E;
+    for (int r0 = 0; r0 < R; r0 += WAVE) {
+      const int r = r0 + lane;
+      double acc = 0;
+      if (r < R) {
+        const double px = x0[((int64_t)g * R + r) * 2], py = x0[((int64_t)g * R + r) * 2 + 1];
+        for (int64_t e = e0; e < e1; ++e) {
+          const int4 m = elem[e];
+          const int o = m.w & 1;
+          const int ci = (m.w >> 4) & 0x3fff;
+          const int cj = (m.w >> 18) & 0x3fff;
+          if (ci == kPadCell && cj == kPadCell) continue;   // batch padding
+          if (!near_cell(ci, cj, h, px, py, lim)) continue;
+          const double* Q = quad + (int64_t)o * nq * (3 + NP);
+          double s = 0;
+          for (int q = 0; q < nq; ++q) {
+            const double X = (ci + Q[q * (3 + NP)]) * h - px;
+            const double Y = (cj + Q[q * (3 + NP) + 1]) * h - py;
+            s += Q[q * (3 + NP) + 2] * exp(-(X * X + Y * Y) * inv2s2);
+          }
+          acc += s * h * h;
         }
-        acc += s * h * h;
       }
+      red[w][lane] = acc;
+      __syncthreads();
+      if (w == 0 && r < R) {
+        double s = red[0][lane];
+        for (int k = 1; k < (int)(blockDim.x / WAVE); ++k) s += red[k][lane];
+        part[(b * R + r) * 6 + 0] = s;
+        for (int c = 1; c < 6; ++c) part[(b * R + r) * 6 + c] = 0.0;
+      }
+      __syncthreads();
     }
-    red[w][lane] = acc;
-    __syncthreads();
-    if (w == 0 && r < R) {
-      double s = red[0][lane];
-      for (int k = 1; k < (int)(blockDim.x / WAVE); ++k) s += red[k][lane];
-      part[(b * R + r) * 6 + 0] = s;
-      for (int c = 1; c < 6; ++c) part[(b * R + r) * 6 + c] = 0.0;
-    }
-    __syncthreads();
   }
 }
 
+// u = M^-1 (sum_q w_q g(x_q) phi(x_q)) / mass, written for every element
+// (zero beyond the cutoff).  mass is [G][R][6] (slot 0).
 template <typename T, int NP>
 __global__ void __launch_bounds__(256) k_ic_project(const int4* __restrict__ elem, int64_t E,
                                                     const double* __restrict__ quad, int nq,
                                                     const double* __restrict__ Minv,
                                                     const double* __restrict__ x0,
+                                                    const int* __restrict__ blk_geom,
                                                     const double* __restrict__ mass, double sigma0,
                                                     double h, double cutoff, int R, int epw,
                                                     int64_t nblocks, T* __restrict__ u) {
-  const int64_t b = logical_block(nblocks);
-  if (b >= (nblocks < 0 ? -nblocks : nblocks)) return;
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
-  const int64_t e1 = e0 + epw < E ? e0 + epw : E;
   const double inv2s2 = 1.0 / (2.0 * sigma0 * sigma0);
   const double lim = cutoff * sigma0;
-  for (int64_t e = e0; e < e1; ++e) {
-    const int4 m = elem[e];
-    const int o = m.w & 1;
-    const int ci = (m.w >> 4) & 0x3fff;
-    const int cj = (m.w >> 18) & 0x3fff;
-    const double* Q = quad + (int64_t)o * nq * (3 + NP);
-    const double* Mi = Minv + o * NP * NP;
-    for (int r = lane; r < R; r += WAVE) {
-      const double px = x0[2 * r], py = x0[2 * r + 1];
-      double c[NP];
+  const BlockIter it = block_iter(nblocks, 1);
+  for (int64_t b = it.first; b < it.end; b += it.stride) {
+    const int g = blk_geom ? blk_geom[b] : 0;
+    const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
+    const int64_t e1 = e0 + epw < E ? e0 + epw : E;
+    for (int64_t e = e0; e < e1; ++e) {
+      const int4 m = elem[e];
+      const int o = m.w & 1;
+      const int ci = (m.w >> 4) & 0x3fff;
+      const int cj = (m.w >> 18) & 0x3fff;
+      const double* Q = quad + (int64_t)o * nq * (3 + NP);
+      const double* Mi = Minv + o * NP * NP;
+      for (int r = lane; r < R; r += WAVE) {
+        const double px = x0[((int64_t)g * R + r) * 2], py = x0[((int64_t)g * R + r) * 2 + 1];
+        double c[NP];
 #pragma unroll
-      for (int j = 0; j < NP; ++j) c[j] = 0;
-      if (near_cell(ci, cj, h, px, py, lim)) {
-        double bq[NP];
+        for (int j = 0; j < NP; ++j) c[j] = 0;
+        if (!(ci == kPadCell && cj == kPadCell) && near_cell(ci, cj, h, px, py, lim)) {
+          double bq[NP];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) bq[j] = 0;
-        for (int q = 0; q < nq; ++q) {
-          const double* Qq = Q + q * (3 + NP);
-          const double X = (ci + Qq[0]) * h - px;
-          const double Y = (cj + Qq[1]) * h - py;
-          const double g = Qq[2] * exp(-(X * X + Y * Y) * inv2s2);
+          for (int j = 0; j < NP; ++j) bq[j] = 0;
+          for (int q = 0; q < nq; ++q) {
+            const double* Qq = Q + q * (3 + NP);
+            const double X = (ci + Qq[0]) * h - px;
+            const double Y = (cj + Qq[1]) * h - py;
+            const double gq = Qq[2] * exp(-(X * X + Y * Y) * inv2s2);
 #pragma unroll
-          for (int j = 0; j < NP; ++j) bq[j] += g * Qq[3 + j];
+            for (int j = 0; j < NP; ++j) bq[j] += gq * Qq[3 + j];
+          }
+          const double s = 1.0 / mass[((int64_t)g * R + r) * 6];
+#pragma unroll
+          for (int i = 0; i < NP; ++i) {
+            double a = 0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) a += Mi[i * NP + j] * bq[j];
+            c[i] = a * s;
+          }
         }
-        const double s = 1.0 / mass[r * 6];
+        const int64_t base = (e * NP) * (int64_t)R + r;
 #pragma unroll
-        for (int i = 0; i < NP; ++i) {
-          double a = 0;
-#pragma unroll
-          for (int j = 0; j < NP; ++j) a += Mi[i * NP + j] * bq[j];
-          c[i] = a * s;
-        }
+        for (int i = 0; i < NP; ++i) u[base + (int64_t)i * R] = (T)c[i];
       }
-      const int64_t base = (e * NP) * (int64_t)R + r;
-#pragma unroll
-      for (int i = 0; i < NP; ++i) u[base + (int64_t)i * R] = (T)c[i];
     }
   }
 }
@@ -327,44 +388,45 @@ __global__ void __launch_bounds__(256) k_dot_mass(const double* __restrict__ x,
                                                   const double* __restrict__ Mass, int R, int epw,
                                                   int64_t nblocks, double* __restrict__ part) {
   __shared__ double red[4][WAVE];
-  const int64_t b = logical_block(nblocks);
-  if (b >= (nblocks < 0 ? -nblocks : nblocks)) return;
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
-  const int64_t e1 = e0 + epw < E ? e0 + epw : E;
-  for (int r0 = 0; r0 < R; r0 += WAVE) {
-    const int r = r0 + lane;
-    double acc = 0;
-    if (r < R) {
-      for (int64_t e = e0; e < e1; ++e) {
-        const int o = elem[e].w & 1;
-        const double* M = Mass + o * NP * NP;
-        const int64_t base = (e * NP) * (int64_t)R + r;
-        double xv[NP], yv[NP];
+  const BlockIter it = block_iter(nblocks, 1);
+  for (int64_t b = it.first; b < it.end; b += it.stride) {
+    const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
+    const int64_t e1 = e0 + epw < E ? e0 + epw : E;
+    for (int r0 = 0; r0 < R; r0 += WAVE) {
+      const int r = r0 + lane;
+      double acc = 0;
+      if (r < R) {
+        for (int64_t e = e0; e < e1; ++e) {
+          const int o = elem[e].w & 1;
+          const double* M = Mass + o * NP * NP;
+          const int64_t base = (e * NP) * (int64_t)R + r;
+          double xv[NP], yv[NP];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) {
-          xv[j] = x[base + (int64_t)j * R];
-          yv[j] = y[base + (int64_t)j * R];
-        }
+          for (int j = 0; j < NP; ++j) {
+            xv[j] = x[base + (int64_t)j * R];
+            yv[j] = y[base + (int64_t)j * R];
+          }
 #pragma unroll
-        for (int i = 0; i < NP; ++i) {
-          double a = 0;
+          for (int i = 0; i < NP; ++i) {
+            double a = 0;
 #pragma unroll
-          for (int j = 0; j < NP; ++j) a += M[i * NP + j] * yv[j];
-          acc += xv[i] * a;
+            for (int j = 0; j < NP; ++j) a += M[i * NP + j] * yv[j];
+            acc += xv[i] * a;
+          }
         }
       }
+      red[w][lane] = acc;
+      __syncthreads();
+      if (w == 0 && r < R) {
+        double s = red[0][lane];
+        for (int k = 1; k < (int)(blockDim.x / WAVE); ++k) s += red[k][lane];
+        part[(b * R + r) * 6 + 0] = s;
+        for (int c = 1; c < 6; ++c) part[(b * R + r) * 6 + c] = 0.0;
+      }
+      __syncthreads();
     }
-    red[w][lane] = acc;
-    __syncthreads();
-    if (w == 0 && r < R) {
-      double s = red[0][lane];
-      for (int k = 1; k < (int)(blockDim.x / WAVE); ++k) s += red[k][lane];
-      part[(b * R + r) * 6 + 0] = s;
-      for (int c = 1; c < 6; ++c) part[(b * R + r) * 6 + c] = 0.0;
-    }
-    __syncthreads();
   }
 }
 
@@ -379,59 +441,37 @@ __global__ void k_fill_random(double* x, int64_t n, uint64_t seed) {
   x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-__global__ void k_scale(double* x, int64_t n, double s) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] *= s;
-}
-
 template <typename T, int NP>
 void stage_t(const void* us, const void* ub, void* out, const int4* elem, int64_t E, const void* S,
              const void* N, int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st) {
   const unsigned chunks = (unsigned)((R + 63) / 64);
   hipLaunchKernelGGL((k_stage<T, NP>), dim3((unsigned)sh.grid, chunks), dim3(64 * sh.waves), 0, st,
                      (const T*)us, (const T*)ub, (T*)out, elem, E, (const double*)S,
-                     (const double*)N, mode, cb, cg, R, sh.epw, sh.blocks);
-}
-
-template <typename T, int NP>
-void moments_t(const void* u, const int4* elem, int64_t E, const double* W, const double* x0,
-               double h, int R, const Shape& sh, double* part, hipStream_t st) {
-  hipLaunchKernelGGL((k_moments<T, NP>), dim3((unsigned)sh.grid), dim3(64 * sh.waves), 0, st,
-                     (const T*)u, elem, E, W, x0, h, R, sh.epw, sh.blocks, part);
-}
-
-template <typename T, int NP>
-void ic_project_t(const int4* elem, int64_t E, const double* quad, int nq, const double* Minv,
-                  const double* x0, const double* mass, double sigma0, double h, double cutoff,
-                  int R, const Shape& sh, void* u, hipStream_t st) {
-  hipLaunchKernelGGL((k_ic_project<T, NP>), dim3((unsigned)sh.grid), dim3(64 * sh.waves), 0, st,
-                     elem, E, quad, nq, Minv, x0, mass, sigma0, h, cutoff, R, sh.epw, sh.blocks,
-                     (T*)u);
+                     (const double*)N, mode, cb, cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0);
 }
 
 }  // namespace
 
-Shape element_shape(int64_t E, int epw, int waves, bool xcd_remap) {
+Shape element_shape(int64_t E, int epw, int waves, bool xcd_remap, int64_t max_grid) {
   Shape s;
   s.epw = epw;
   s.waves = waves;
+  s.remap = xcd_remap;
   const int64_t per_block = (int64_t)s.waves * epw;
   s.blocks = (E + per_block - 1) / per_block;
   if (s.blocks < 1) s.blocks = 1;
-  s.grid = (s.blocks + 7) / 8 * 8;
-  if (!xcd_remap) {
-    s.grid = s.blocks;
-    s.blocks = -s.blocks;     // identity mapping (see logical_block)
-  }
+  s.grid = s.blocks;
+  if (max_grid > 0 && s.grid > max_grid) s.grid = max_grid;   // persistent
+  if (s.remap) s.grid = (s.grid + 7) / 8 * 8;
   return s;
 }
 
-#define DGD_DISPATCH_NP(np, ...)                         \
-  switch (np) {                                          \
-    case 3: { constexpr int NP = 3; __VA_ARGS__; break; }  \
-    case 6: { constexpr int NP = 6; __VA_ARGS__; break; }  \
-    case 10: { constexpr int NP = 10; __VA_ARGS__; break; } \
-    default: break;                                      \
+#define DGD_DISPATCH_NP(np, ...)                              \
+  switch (np) {                                               \
+    case 3: { constexpr int NP = 3; __VA_ARGS__; break; }     \
+    case 6: { constexpr int NP = 6; __VA_ARGS__; break; }     \
+    case 10: { constexpr int NP = 10; __VA_ARGS__; break; }   \
+    default: break;                                           \
   }
 
 void launch_stage(int prec, int np, const void* us, const void* ub, void* out, const int4* elem,
@@ -445,35 +485,46 @@ void launch_stage(int prec, int np, const void* us, const void* ub, void* out, c
 }
 
 void launch_moments(int prec, int np, const void* u, const int4* elem, int64_t E, const double* W,
-                    const double* x0, double h, int R, const Shape& sh, double* part, hipStream_t st) {
+                    const double* x0, const int* blk_geom, double h, int R, const Shape& sh,
+                    double* part, hipStream_t st) {
+  const dim3 grid((unsigned)sh.grid), block(64 * sh.waves);
   if (prec == 0) {
-    DGD_DISPATCH_NP(np, moments_t<double, NP>(u, elem, E, W, x0, h, R, sh, part, st));
+    DGD_DISPATCH_NP(np, k_moments<double, NP><<<grid, block, 0, st>>>(
+                            (const double*)u, elem, E, W, x0, blk_geom, h, R, sh.epw, sh.blocks,
+                            part));
   } else {
-    DGD_DISPATCH_NP(np, moments_t<float, NP>(u, elem, E, W, x0, h, R, sh, part, st));
+    DGD_DISPATCH_NP(np, k_moments<float, NP><<<grid, block, 0, st>>>(
+                            (const float*)u, elem, E, W, x0, blk_geom, h, R, sh.epw, sh.blocks,
+                            part));
   }
 }
 
-void launch_reduce(const double* part, int nblk, int R, double* out, hipStream_t st) {
-  const int n = R * 6;
-  hipLaunchKernelGGL(k_reduce, dim3((n + 255) / 256), dim3(256), 0, st, part, nblk, R, out);
+void launch_reduce(const double* part, const int* blk_start, int G, int R, double* out,
+                   hipStream_t st) {
+  k_reduce_seg<<<dim3((unsigned)(G * R * 6)), dim3(64), 0, st>>>(part, blk_start, G, R, out);
 }
 
 void launch_ic_mass(int np, const int4* elem, int64_t E, const double* quad, int nq,
-                    const double* x0, double sigma0, double h, double cutoff, int R, const Shape& sh,
-                    double* part, hipStream_t st) {
+                    const double* x0, const int* blk_geom, double sigma0, double h, double cutoff,
+                    int R, const Shape& sh, double* part, hipStream_t st) {
   DGD_DISPATCH_NP(np, k_ic_mass<NP><<<dim3((unsigned)sh.grid), dim3(64 * sh.waves), 0, st>>>(
-                          elem, E, quad, nq, x0, sigma0, h, cutoff, R, sh.epw, sh.blocks, part));
+                          elem, E, quad, nq, x0, blk_geom, sigma0, h, cutoff, R, sh.epw,
+                          sh.blocks, part));
 }
 
 void launch_ic_project(int prec, int np, const int4* elem, int64_t E, const double* quad, int nq,
-                       const double* Minv, const double* x0, const double* mass, double sigma0,
-                       double h, double cutoff, int R, const Shape& sh, void* u, hipStream_t st) {
+                       const double* Minv, const double* x0, const int* blk_geom,
+                       const double* mass, double sigma0, double h, double cutoff, int R,
+                       const Shape& sh, void* u, hipStream_t st) {
+  const dim3 grid((unsigned)sh.grid), block(64 * sh.waves);
   if (prec == 0) {
-    DGD_DISPATCH_NP(np, ic_project_t<double, NP>(elem, E, quad, nq, Minv, x0, mass, sigma0, h,
-                                                  cutoff, R, sh, u, st));
+    DGD_DISPATCH_NP(np, k_ic_project<double, NP><<<grid, block, 0, st>>>(
+                            elem, E, quad, nq, Minv, x0, blk_geom, mass, sigma0, h, cutoff, R,
+                            sh.epw, sh.blocks, (double*)u));
   } else {
-    DGD_DISPATCH_NP(np, ic_project_t<float, NP>(elem, E, quad, nq, Minv, x0, mass, sigma0, h,
-                                                 cutoff, R, sh, u, st));
+    DGD_DISPATCH_NP(np, k_ic_project<float, NP><<<grid, block, 0, st>>>(
+                            elem, E, quad, nq, Minv, x0, blk_geom, mass, sigma0, h, cutoff, R,
+                            sh.epw, sh.blocks, (float*)u));
   }
 }
 
@@ -485,10 +536,6 @@ void launch_dot_mass(int np, const double* x, const double* y, const int4* elem,
 
 void launch_fill_random(double* x, int64_t n, uint64_t seed, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_random, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, seed);
-}
-
-void launch_scale(double* x, int64_t n, double s, hipStream_t st) {
-  hipLaunchKernelGGL(k_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, s);
 }
 
 }  // namespace dgd

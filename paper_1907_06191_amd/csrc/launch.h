@@ -7,43 +7,50 @@
 
 namespace dgd {
 
-// Launch shape shared by the element kernels: 256-thread workgroups (four
-// 64-wide waves), each wave walking `epw` consecutive elements with its
-// lanes on right-hand sides.  Blocks are remapped so that each of the eight
-// XCDs sweeps one contiguous band of elements.
+// Launch shape shared by the element kernels: workgroups of `waves` 64-wide
+// waves, each wave walking `epw` consecutive elements with its lanes on
+// right-hand sides.  `blocks` logical blocks cover the elements; `grid`
+// workgroups are launched (fewer than `blocks` makes the kernel persistent).
+// With `remap`, each of the eight XCDs sweeps one contiguous band of blocks.
 struct Shape {
-  int epw = 4;          // elements per wave
-  int waves = 4;        // waves per workgroup (<= 4: the reductions use 4-wave LDS arrays)
-  int64_t blocks = 0;   // logical blocks (negative: identity block mapping, |blocks| blocks)
-  int64_t grid = 0;     // launched blocks (multiple of 8 with the XCD remap)
-  int64_t nblk() const { return blocks < 0 ? -blocks : blocks; }
+  int epw = 1;
+  int waves = 4;        // <= 4: the reduction kernels use 4-wave LDS arrays
+  bool remap = true;
+  int64_t blocks = 0;
+  int64_t grid = 0;
 };
-Shape element_shape(int64_t E, int epw, int waves = 4, bool xcd_remap = true);
+Shape element_shape(int64_t E, int epw, int waves = 4, bool xcd_remap = true, int64_t max_grid = 0);
 
 // One SSP-RK3 stage (mode 1) or a plain operator apply (mode 0):
 //   mode 0: out = cg * L(us)
 //   mode 1: out = base + cb * (us - base) + cg * L(us), base = ub (or us when ub is NULL)
 // with L(us)_K = S_{o,mask}(us_K - c) + sum_f N_{o,f}(us_f - c), c = us_K[node 0]
-// per right-hand side.  `ub` may equal `out`.
+// per right-hand side; S, N are FP64.  `ub` may equal `out`.
 void launch_stage(int prec, int np, const void* us, const void* ub, void* out, const int4* elem,
                   int64_t E, const void* S, const void* N, int mode, double cb, double cg, int R,
                   const Shape& sh, hipStream_t st);
 
-// FP64 moment partial sums per block: part[b][r][6].
+// FP64 moment partial sums per logical block: part[b][r][6].  x0 is
+// [G][R][2]; blk_geom (NULL when G = 1) gives the geometry of each block.
 void launch_moments(int prec, int np, const void* u, const int4* elem, int64_t E, const double* W,
-                    const double* x0, double h, int R, const Shape& sh, double* part, hipStream_t st);
-
-// Deterministic sum of partials over blocks: out[r][c] = sum_b part[b][r][c], c < 6.
-void launch_reduce(const double* part, int nblk, int R, double* out, hipStream_t st);
-
-// Initial data.  Mass pass writes part[b][r][0] = sum of h^2 w_q g(x_q) over
-// the block's elements; project pass writes u = M^-1 (sum_q w_q g phi) / mass.
-void launch_ic_mass(int np, const int4* elem, int64_t E, const double* quad, int nq,
-                    const double* x0, double sigma0, double h, double cutoff, int R, const Shape& sh,
+                    const double* x0, const int* blk_geom, double h, int R, const Shape& sh,
                     double* part, hipStream_t st);
+
+// out[g][r][c] = sum over the blocks of geometry g (blk_start[g] ..
+// blk_start[g+1]) of part[b][r][c], in a fixed order.
+void launch_reduce(const double* part, const int* blk_start, int G, int R, double* out,
+                   hipStream_t st);
+
+// Initial data.  The mass pass writes part[b][r][0] = sum of h^2 w_q g(x_q)
+// over the block's elements; the project pass writes
+// u = M^-1 (sum_q w_q g phi) / mass[g][r].
+void launch_ic_mass(int np, const int4* elem, int64_t E, const double* quad, int nq,
+                    const double* x0, const int* blk_geom, double sigma0, double h, double cutoff,
+                    int R, const Shape& sh, double* part, hipStream_t st);
 void launch_ic_project(int prec, int np, const int4* elem, int64_t E, const double* quad, int nq,
-                       const double* Minv, const double* x0, const double* mass, double sigma0,
-                       double h, double cutoff, int R, const Shape& sh, void* u, hipStream_t st);
+                       const double* Minv, const double* x0, const int* blk_geom,
+                       const double* mass, double sigma0, double h, double cutoff, int R,
+                       const Shape& sh, void* u, hipStream_t st);
 
 // part[b][r][0] = sum over the block's elements of x_K^T Mhat y_K (FP64).
 void launch_dot_mass(int np, const double* x, const double* y, const int4* elem, int64_t E,
@@ -51,6 +58,5 @@ void launch_dot_mass(int np, const double* x, const double* y, const int4* elem,
 
 // x[i] = deterministic pseudo-random value in [-1, 1) from (seed, i).
 void launch_fill_random(double* x, int64_t n, uint64_t seed, hipStream_t st);
-void launch_scale(double* x, int64_t n, double s, hipStream_t st);
 
 }  // namespace dgd

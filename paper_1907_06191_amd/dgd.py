@@ -72,6 +72,15 @@ _sig("dgd_run_moments", [_vp, _c_dp])
 _sig("dgd_run_get_state", [_vp, _vp])
 _sig("dgd_run_set_state", [_vp, _vp])
 _sig("dgd_run_destroy", [_vp], None)
+_sig("dgd_batch_workspace_size", [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)])
+_sig("dgd_batch_create", [_vp, ctypes.c_int32, _c_dp, ctypes.c_int32, ctypes.c_double, _vp, ctypes.c_size_t,
+                          _vp, ctypes.POINTER(_vp)])
+_sig("dgd_batch_groups", [_vp, ctypes.POINTER(ctypes.c_int32), _vp, _vp, _vp, _vp])
+_sig("dgd_batch_advance", [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_double])
+_sig("dgd_batch_moments", [_vp, _c_dp])
+_sig("dgd_batch_destroy", [_vp], None)
+_sig("dgd_eap_solve_batch", [_vp, ctypes.c_int32, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp,
+                             ctypes.c_int32, _c_dp, _c_dp, _vp, ctypes.c_size_t, _vp])
 _sig("dgd_eap_solve", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, ctypes.c_int32, _c_dp,
                        _c_dp, _vp, ctypes.c_size_t, _vp])
 
@@ -234,6 +243,70 @@ def dgd_eap_solve(op, points, sigma0: float, deltas, workspace=None, ws_bytes: i
     return sig, mom
 
 
+def _op_array(ops):
+    handles = [o.handle if hasattr(o, "handle") else o for o in ops]
+    return (_vp * len(handles))(*handles)
+
+
+def dgd_batch_workspace_size(ops, n_points: int) -> int:
+    b = ctypes.c_size_t()
+    _check(_lib.dgd_batch_workspace_size(_op_array(ops), len(ops), int(n_points), ctypes.byref(b)))
+    return b.value
+
+
+def dgd_batch_create(ops, points, sigma0: float, workspace=None, ws_bytes: int = 0, stream=None) -> int:
+    pts = _f64(points).reshape(len(ops), -1, 2)
+    out = _vp()
+    if workspace is not None and not ws_bytes:
+        ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib.dgd_batch_create(_op_array(ops), len(ops), _ptr(pts), int(pts.shape[1]), float(sigma0),
+                                 _dev_ptr(workspace), int(ws_bytes), _stream_ptr(stream), ctypes.byref(out)))
+    return out.value
+
+
+def dgd_batch_groups(batch):
+    n = ctypes.c_int32()
+    _check(_lib.dgd_batch_groups(batch, ctypes.byref(n), None, None, None, None))
+    p = np.zeros(n.value, dtype=np.int32)
+    size = np.zeros(n.value, dtype=np.int32)
+    dt = np.zeros(n.value)
+    dof = np.zeros(n.value, dtype=np.int64)
+    _check(_lib.dgd_batch_groups(batch, ctypes.byref(n), p.ctypes.data, size.ctypes.data, dt.ctypes.data,
+                                 dof.ctypes.data))
+    return [dict(p=int(p[k]), size=int(size[k]), dt=float(dt[k]), dof=int(dof[k])) for k in range(n.value)]
+
+
+def dgd_batch_advance(batch, group: int, n_steps: int, dt_ms: float) -> None:
+    _check(_lib.dgd_batch_advance(batch, int(group), int(n_steps), float(dt_ms)))
+
+
+def dgd_batch_moments(batch, n_geoms: int, n_points: int, check: bool = True) -> np.ndarray:
+    out = np.zeros((n_geoms, n_points, 6))
+    rc = _lib.dgd_batch_moments(batch, _ptr(out))
+    if check:
+        _check(rc)
+    return out
+
+
+def dgd_batch_destroy(batch) -> None:
+    _lib.dgd_batch_destroy(batch)
+
+
+def dgd_eap_solve_batch(ops, points, sigma0: float, deltas, workspace=None, ws_bytes: int = 0, stream=None):
+    """Returns (sigma [G][n][nDelta][3], moments [G][n][nDelta][6])."""
+    pts = _f64(points).reshape(len(ops), -1, 2)
+    d = _f64(deltas).ravel()
+    G, n = pts.shape[0], pts.shape[1]
+    sig = np.zeros((G, n, d.size, 3))
+    mom = np.zeros((G, n, d.size, 6))
+    if workspace is not None and not ws_bytes:
+        ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib.dgd_eap_solve_batch(_op_array(ops), G, _ptr(pts), n, float(sigma0), _ptr(d), int(d.size),
+                                    _ptr(sig), _ptr(mom), _dev_ptr(workspace), int(ws_bytes),
+                                    _stream_ptr(stream)))
+    return sig, mom
+
+
 # ----------------------------------------------------------- RAII helpers
 
 class Mesh:
@@ -281,6 +354,33 @@ class Operator:
 
     def solve(self, points, sigma0, deltas, workspace=None, stream=None):
         return dgd_eap_solve(self.handle, points, sigma0, deltas, workspace=workspace, stream=stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+class Batch:
+    def __init__(self, ops, points, sigma0, workspace=None, stream=None):
+        self._destroy = _lib.dgd_batch_destroy
+        self.ops = list(ops)
+        pts = np.asarray(points, dtype=np.float64).reshape(len(self.ops), -1, 2)
+        self.G, self.n = pts.shape[0], pts.shape[1]
+        self.workspace = workspace
+        self.handle = dgd_batch_create(self.ops, pts, sigma0, workspace=workspace, stream=stream)
+
+    def groups(self):
+        return dgd_batch_groups(self.handle)
+
+    def advance(self, group, n_steps, dt_ms):
+        dgd_batch_advance(self.handle, group, n_steps, dt_ms)
+
+    def moments(self, check=True):
+        return dgd_batch_moments(self.handle, self.G, self.n, check)
 
     def close(self):
         if getattr(self, "handle", None):

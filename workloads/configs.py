@@ -63,3 +63,25 @@ def c3_geometry_params(g: int) -> dict:
     return dict(N=N, L=N * h, phi=phi, shape=shape, mean=mean, p=p,
                 geom_seed=BASE_SEED + 300 + 1000 * g + 7,
                 point_seed=BASE_SEED + 301 + 1000 * g)
+
+
+def _c3_one(g):
+    from .geometry import make_geometry, start_points
+    prm = c3_geometry_params(g)
+    # proposals drawn 2048 at a time: the densest of these packings jam
+    geo = make_geometry(prm["L"], prm["N"], prm["geom_seed"], phi=prm["phi"],
+                        shape=prm["shape"], mean=prm["mean"], batch=2048)
+    pts = start_points(geo.disks, geo.L, geo.N, CONFIGS["C3"]["R"],
+                       np.random.default_rng(prm["point_seed"]))
+    return geo, pts, prm["p"]
+
+
+def c3_workload(n_geoms: int | None = None, workers: int = 1):
+    """[(Geometry, start points [16, 2], p)] for the batched workload's
+    geometries 0 .. n_geoms-1 (all 256 by default), drawn in parallel."""
+    n = CONFIGS["C3"]["n_geoms"] if n_geoms is None else n_geoms
+    if workers <= 1:
+        return [_c3_one(g) for g in range(n)]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_c3_one, range(n), chunksize=1)

@@ -10,7 +10,9 @@ produce seeded stand-ins:
   disk area reaches phi * L**2 -- and placed largest first.  Each disk gets at
   most ``max_tries`` uniform centre proposals in [0, L]^2 and is accepted at
   the first proposal whose gap to every placed disk is at least ``gap``;
-  a disk that finds no place is dropped.  Disks may cross the box edge.
+  a disk that finds no place is dropped, and after ``max_fail_run``
+  consecutive dropped disks the packing counts as jammed and placement
+  stops.  Disks may cross the box edge.
 * ``start_points``: points uniform in the centred box of side ``box_frac*L``
   (the paper draws its pulses in a centred 20 um box of a 50 um square,
   section 4.2), rejected when closer than r + sqrt(2)*h to a disk centre, so
@@ -65,7 +67,8 @@ def _draw_radii(rng, L, phi, n_disks, shape, mean):
 
 def rsa_disks(L: float, rng: np.random.Generator, *, phi: float | None = None,
               n_disks: int | None = None, shape: float = 4.0, mean: float = 0.5,
-              gap: float = 0.1, max_tries: int = 20000, batch: int = 256) -> np.ndarray:
+              gap: float = 0.1, max_tries: int = 20000, batch: int = 256,
+              max_fail_run: int = 64) -> np.ndarray:
     """Random sequential addition of Gamma-radius disks in [0, L]^2.
 
     Exactly one of ``phi`` (target summed disk area / L^2) and ``n_disks``
@@ -76,51 +79,60 @@ def rsa_disks(L: float, rng: np.random.Generator, *, phi: float | None = None,
     radii = _draw_radii(rng, L, phi, n_disks, shape, mean)
     if radii.size == 0:
         return np.zeros((0, 3))
-    rmax = float(radii[0])
-    cell = 2.0 * rmax + gap
+    # Exclusion lookup on a fine grid: disk j is registered in every cell its
+    # zone of radius 2 r_j + gap touches.  Radii are placed in decreasing
+    # order, so a later disk of radius r <= r_j clashes with j only at
+    # proposal points inside that zone: one cell lookup finds every clash.
+    cell = max(0.25, float(np.mean(radii)))
     ng = max(1, int(math.ceil(L / cell)))
-    cap = 8
-    grid = -np.ones((ng + 2, ng + 2, cap), dtype=np.int64)   # padded by one ring
-    count = np.zeros((ng + 2, ng + 2), dtype=np.int64)
+    cap = 16
+    grid = -np.ones((ng, ng, cap), dtype=np.int64)
+    count = np.zeros((ng, ng), dtype=np.int64)
     placed = np.zeros((radii.size, 3))
     n = 0
-    offs = np.array([(dx, dy) for dx in (-1, 0, 1) for dy in (-1, 0, 1)])
+    fail_run = 0
     for r in radii:
+        if fail_run >= max_fail_run:
+            break
         tries = 0
         done = False
         while tries < max_tries and not done:
             k = min(batch, max_tries - tries)
             prop = rng.uniform(0.0, L, size=(k, 2))
             tries += k
-            gx = np.minimum((prop[:, 0] / cell).astype(np.int64), ng - 1) + 1
-            gy = np.minimum((prop[:, 1] / cell).astype(np.int64), ng - 1) + 1
-            cx = gx[:, None] + offs[None, :, 0]
-            cy = gy[:, None] + offs[None, :, 1]
-            cand = grid[cx, cy]                      # [k, 9, cap]
-            ok = np.ones(k, dtype=bool)
+            gx = np.minimum((prop[:, 0] / cell).astype(np.int64), ng - 1)
+            gy = np.minimum((prop[:, 1] / cell).astype(np.int64), ng - 1)
+            cand = grid[gx, gy]                      # [k, cap]
             valid = cand >= 0
+            ok = np.ones(k, dtype=bool)
             if valid.any():
                 ci = np.where(valid, cand, 0)
-                px = placed[ci, 0]
-                py = placed[ci, 1]
-                pr = placed[ci, 2]
-                dx = px - prop[:, 0, None, None]
-                dy = py - prop[:, 1, None, None]
-                need = pr + r + gap
-                clash = valid & (dx * dx + dy * dy < need * need)
-                ok = ~clash.any(axis=(1, 2))
+                dx = placed[ci, 0] - prop[:, 0, None]
+                dy = placed[ci, 1] - prop[:, 1, None]
+                need = placed[ci, 2] + r + gap
+                ok = ~(valid & (dx * dx + dy * dy < need * need)).any(axis=1)
             idx = np.flatnonzero(ok)
             if idx.size:
                 j = int(idx[0])
-                placed[n] = (prop[j, 0], prop[j, 1], r)
-                a, b = int(gx[j]), int(gy[j])
-                if count[a, b] == cap:
+                x, y = float(prop[j, 0]), float(prop[j, 1])
+                placed[n] = (x, y, r)
+                zr = 2.0 * r + gap
+                i0, i1 = max(0, int((x - zr) / cell)), min(ng - 1, int((x + zr) / cell))
+                j0, j1 = max(0, int((y - zr) / cell)), min(ng - 1, int((y + zr) / cell))
+                ii, jj = np.meshgrid(np.arange(i0, i1 + 1), np.arange(j0, j1 + 1), indexing="ij")
+                # distance from the centre to each cell rectangle
+                ddx = np.maximum(np.maximum(ii * cell - x, x - (ii + 1) * cell), 0.0)
+                ddy = np.maximum(np.maximum(jj * cell - y, y - (jj + 1) * cell), 0.0)
+                hit = ddx * ddx + ddy * ddy < zr * zr
+                ii, jj = ii[hit], jj[hit]
+                if ii.size and count[ii, jj].max() >= cap:
                     grid = np.concatenate([grid, -np.ones_like(grid)], axis=2)
                     cap *= 2
-                grid[a, b, count[a, b]] = n
-                count[a, b] += 1
+                grid[ii, jj, count[ii, jj]] = n
+                count[ii, jj] += 1
                 n += 1
                 done = True
+        fail_run = 0 if done else fail_run + 1
     return placed[:n].copy()
 
 
@@ -174,14 +186,14 @@ def start_points(disks: np.ndarray, L: float, N: int, m: int,
 
 
 def make_geometry(L: float, N: int, seed: int, *, phi=None, n_disks=None,
-                  shape=4.0, mean=0.5, gap=0.1) -> Geometry:
+                  shape=4.0, mean=0.5, gap=0.1, batch=256) -> Geometry:
     """Seeded disk packing on an N x N grid over [0, L]^2."""
     rng = np.random.default_rng(seed)
     if phi is None and n_disks is None:
         disks = np.zeros((0, 3))
     else:
         disks = rsa_disks(L, rng, phi=phi, n_disks=n_disks, shape=shape,
-                          mean=mean, gap=gap)
+                          mean=mean, gap=gap, batch=batch)
     params = dict(L=L, N=N, seed=seed, phi_target=phi, n_disks_target=n_disks,
                   gamma_shape=shape, gamma_mean=mean, gap=gap,
                   n_disks=int(disks.shape[0]))
