@@ -217,6 +217,53 @@ int dgd_eap_solve_batch(dgd_op* const* ops, int32_t n_geoms, const double* point
                         int32_t n_deltas, double* sigma_out, double* moments_out, void* d_ws,
                         size_t ws_bytes, void* hip_stream);
 
+/*
+ * Occupancy image of a mesh: image_out host uint8 [size][size], row j (y)
+ * slow, column i (x) fast; a pixel is 1 when the grid cell holding the
+ * pixel centre ((i + 1/2) L / size, (j + 1/2) L / size) is a removed (axon)
+ * cell, else 0.  With size = n_cells the image is the removed-cell mask.
+ */
+int dgd_mesh_occupancy(const dgd_mesh* mesh, int32_t size, uint8_t* image_out);
+
+/*
+ * Learned surrogate (no counterpart in the paper): an ensemble of small
+ * networks mapping a 64 x 64 occupancy image and log(Delta / 1 ms) to the
+ * three unique entries (xx, xy, yy) of Sigma / (2 D Delta).  Each member:
+ * 4 x [conv 3x3 zero-pad -> `channels` maps, ReLU, 2x2 average pool],
+ * flatten, append log Delta, 3 x [dense `hidden` units, ReLU], dense 3.
+ * Training: mean squared error, Adam (beta 0.9 / 0.999, eps 1e-8), FP32,
+ * all forward and backward steps in the library's kernels; every reduction
+ * has a fixed order, so results are reproducible bit for bit.
+ */
+typedef struct dgd_surrogate dgd_surrogate;
+/* n_members in [1, 64], channels in [1, 32], hidden in [1, 4096]; weights
+ * He-uniform from `seed` (member m uses seed + 7919 m), biases zero. */
+int dgd_surrogate_create(int32_t n_members, int32_t channels, int32_t hidden, uint64_t seed,
+                         dgd_surrogate** out);
+int dgd_surrogate_n_params(const dgd_surrogate* s, int64_t* n);
+/* Parameters of one member as one float32 vector (layer order conv1.w,
+ * conv1.b, .., conv4.b, fc1.w [hidden][16 channels + 1], fc1.b, fc2.w,
+ * fc2.b, fc3.w, fc3.b, head.w [3][hidden], head.b). */
+int dgd_surrogate_get_params(const dgd_surrogate* s, int32_t member, float* host_out);
+int dgd_surrogate_set_params(dgd_surrogate* s, int32_t member, const float* host_in);
+/* Loss and gradient of one member on n <= 4096 samples (no update):
+ * images uint8 [n][64][64] in {0, 1}, log_deltas [n], targets [n][3]. */
+int dgd_surrogate_loss_grad(dgd_surrogate* s, int32_t member, const uint8_t* images,
+                            const double* log_deltas, const double* targets, int32_t n,
+                            double* loss_out, float* grad_out);
+/* `epochs` passes of mini-batch Adam per member over shuffled full batches
+ * of `batch` samples (shuffle from shuffle_seed); epoch_loss_out NULL or
+ * [n_members][epochs] mean squared error. */
+int dgd_surrogate_train(dgd_surrogate* s, const uint8_t* images, const double* log_deltas,
+                        const double* targets, int32_t n, int32_t epochs, int32_t batch,
+                        double lr, uint64_t shuffle_seed, double* epoch_loss_out);
+/* Ensemble mean [n][3], spread [n] = max over outputs of (max - min) over
+ * members (nullable), fallback [n] = spread > threshold (nullable). */
+int dgd_surrogate_predict(dgd_surrogate* s, const uint8_t* images, const double* log_deltas,
+                          int32_t n, double threshold, double* mean_out, double* spread_out,
+                          uint8_t* fallback_out);
+void dgd_surrogate_destroy(dgd_surrogate* s);
+
 /* Runtime options (process-wide; read when a run is created or advanced):
  *   "graphs"       1 = replay steps from captured HIP graphs, 0 = plain launches
  *   "graph_steps"  steps captured per graph, 1..4096

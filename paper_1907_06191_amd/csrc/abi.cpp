@@ -536,6 +536,20 @@ int dgd_mesh_elements(const dgd_mesh* mesh, int32_t* cell_i, int32_t* cell_j, in
   });
 }
 
+int dgd_mesh_occupancy(const dgd_mesh* mesh, int32_t size, uint8_t* image_out) {
+  return guarded([&]() -> int {
+    if (!mesh || !image_out || size < 1 || size > 16384) fail(DGD_EINVAL, "bad argument");
+    const MeshHost& m = mesh->host;
+    for (int j = 0; j < size; ++j)
+      for (int i = 0; i < size; ++i) {
+        const int ci = std::min(m.N - 1, (int)(((i + 0.5) / size) * m.N));
+        const int cj = std::min(m.N - 1, (int)(((j + 0.5) / size) * m.N));
+        image_out[(size_t)j * size + i] = m.active_cell[(size_t)cj * m.N + ci] ? 0 : 1;
+      }
+    return DGD_OK;
+  });
+}
+
 void dgd_mesh_destroy(dgd_mesh* mesh) {
   if (!mesh) return;
   if (mesh->d_elem) (void)hipFree(mesh->d_elem);

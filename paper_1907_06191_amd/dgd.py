@@ -81,6 +81,16 @@ _sig("dgd_batch_moments", [_vp, _c_dp])
 _sig("dgd_batch_destroy", [_vp], None)
 _sig("dgd_eap_solve_batch", [_vp, ctypes.c_int32, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp,
                              ctypes.c_int32, _c_dp, _c_dp, _vp, ctypes.c_size_t, _vp])
+_sig("dgd_mesh_occupancy", [_vp, ctypes.c_int32, _vp])
+_sig("dgd_surrogate_create", [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(_vp)])
+_sig("dgd_surrogate_n_params", [_vp, ctypes.POINTER(ctypes.c_int64)])
+_sig("dgd_surrogate_get_params", [_vp, ctypes.c_int32, _vp])
+_sig("dgd_surrogate_set_params", [_vp, ctypes.c_int32, _vp])
+_sig("dgd_surrogate_loss_grad", [_vp, ctypes.c_int32, _vp, _c_dp, _c_dp, ctypes.c_int32, _c_dp, _vp])
+_sig("dgd_surrogate_train", [_vp, _vp, _c_dp, _c_dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                             ctypes.c_double, ctypes.c_uint64, _c_dp])
+_sig("dgd_surrogate_predict", [_vp, _vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, _c_dp, _vp])
+_sig("dgd_surrogate_destroy", [_vp], None)
 _sig("dgd_eap_solve", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, ctypes.c_int32, _c_dp,
                        _c_dp, _vp, ctypes.c_size_t, _vp])
 
@@ -243,6 +253,77 @@ def dgd_eap_solve(op, points, sigma0: float, deltas, workspace=None, ws_bytes: i
     return sig, mom
 
 
+def dgd_mesh_occupancy(mesh, size: int = 64) -> np.ndarray:
+    img = np.zeros((size, size), dtype=np.uint8)
+    _check(_lib.dgd_mesh_occupancy(mesh, int(size), img.ctypes.data))
+    return img
+
+
+def _u8(images):
+    return np.ascontiguousarray(np.asarray(images, dtype=np.uint8))
+
+
+def dgd_surrogate_create(n_members: int, channels: int = 32, hidden: int = 256, seed: int = 0) -> int:
+    out = _vp()
+    _check(_lib.dgd_surrogate_create(int(n_members), int(channels), int(hidden), int(seed), ctypes.byref(out)))
+    return out.value
+
+
+def dgd_surrogate_n_params(s) -> int:
+    n = ctypes.c_int64()
+    _check(_lib.dgd_surrogate_n_params(s, ctypes.byref(n)))
+    return n.value
+
+
+def dgd_surrogate_get_params(s, member: int) -> np.ndarray:
+    p = np.zeros(dgd_surrogate_n_params(s), dtype=np.float32)
+    _check(_lib.dgd_surrogate_get_params(s, int(member), p.ctypes.data))
+    return p
+
+
+def dgd_surrogate_set_params(s, member: int, params) -> None:
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    _check(_lib.dgd_surrogate_set_params(s, int(member), p.ctypes.data))
+
+
+def dgd_surrogate_loss_grad(s, member: int, images, log_deltas, targets):
+    im = _u8(images)
+    ld = _f64(log_deltas).ravel()
+    tg = _f64(targets, (3,))
+    g = np.zeros(dgd_surrogate_n_params(s), dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(_lib.dgd_surrogate_loss_grad(s, int(member), im.ctypes.data, _ptr(ld), _ptr(tg), int(ld.size),
+                                        ctypes.byref(loss), g.ctypes.data))
+    return loss.value, g
+
+
+def dgd_surrogate_train(s, images, log_deltas, targets, epochs: int, batch: int, lr: float,
+                        shuffle_seed: int, n_members: int) -> np.ndarray:
+    im = _u8(images)
+    ld = _f64(log_deltas).ravel()
+    tg = _f64(targets, (3,))
+    losses = np.zeros((n_members, max(int(epochs), 1)))
+    _check(_lib.dgd_surrogate_train(s, im.ctypes.data, _ptr(ld), _ptr(tg), int(ld.size), int(epochs), int(batch),
+                                    float(lr), int(shuffle_seed), _ptr(losses)))
+    return losses[:, :epochs]
+
+
+def dgd_surrogate_predict(s, images, log_deltas, threshold: float):
+    im = _u8(images)
+    ld = _f64(log_deltas).ravel()
+    n = ld.size
+    mean = np.zeros((n, 3))
+    spread = np.zeros(n)
+    flag = np.zeros(n, dtype=np.uint8)
+    _check(_lib.dgd_surrogate_predict(s, im.ctypes.data, _ptr(ld), n, float(threshold), _ptr(mean),
+                                      _ptr(spread), flag.ctypes.data))
+    return mean, spread, flag.astype(bool)
+
+
+def dgd_surrogate_destroy(s) -> None:
+    _lib.dgd_surrogate_destroy(s)
+
+
 def _op_array(ops):
     handles = [o.handle if hasattr(o, "handle") else o for o in ops]
     return (_vp * len(handles))(*handles)
@@ -381,6 +462,28 @@ class Batch:
 
     def moments(self, check=True):
         return dgd_batch_moments(self.handle, self.G, self.n, check)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+class Surrogate:
+    def __init__(self, n_members=4, channels=32, hidden=256, seed=0):
+        self._destroy = _lib.dgd_surrogate_destroy
+        self.n_members = n_members
+        self.handle = dgd_surrogate_create(n_members, channels, hidden, seed)
+
+    def train(self, images, log_deltas, targets, epochs, batch=256, lr=1e-3, shuffle_seed=0):
+        return dgd_surrogate_train(self.handle, images, log_deltas, targets, epochs, batch, lr, shuffle_seed,
+                                   self.n_members)
+
+    def predict(self, images, log_deltas, threshold=1e-3):
+        return dgd_surrogate_predict(self.handle, images, log_deltas, threshold)
 
     def close(self):
         if getattr(self, "handle", None):
