@@ -271,6 +271,9 @@ void dgd_surrogate_destroy(dgd_surrogate* s);
  *   "stage_waves"  waves per workgroup of the stage kernel, 1..4
  *   "xcd_remap"    1 = each XCD sweeps one contiguous band of elements
  *   "stage_grid"   > 0: persistent stage kernel with this many workgroups
+ *   "p3_mfma"      1 = P3 stages with FP32 state run on matrix cores
+ *                  (v_mfma_f32_16x16x4_f32, FP64 mass correction) when the
+ *                  right-hand-side count is a multiple of 16
  *   "mesh_strip"   element order of meshes created afterwards: vertical strips
  *                  of this many cell columns, each row-major (0 = plain rows)
  * Errors: EINVAL for an unknown name or a value out of range. */

@@ -38,6 +38,7 @@ struct Options {
   bool xcd_remap = true;    // XCD-banded block order
   int64_t stage_grid = 0;   // > 0: persistent stage kernel with this many workgroups
   int mesh_strip = 64;      // element order: vertical strips of this many cell columns (0: rows)
+  bool p3_mfma = true;      // P3 FP32 stages on matrix cores when R % 16 == 0
 };
 Options g_opt;
 
@@ -124,7 +125,71 @@ RunTarget plain_target(const dgd_op* op) {
   t.nq = op->nq;
   t.G = 1;
   t.nblk_red = reduce_shape(t.E).blocks;
+  t.Atab = op->d_Atab;
+  t.Ctab = op->d_Ctab;
+  t.Wtab = op->d_Wtab;
+  t.wsum = op->wsum;
   return t;
+}
+
+// Whether a stage on (E, R) takes the P3 matrix-core kernel.
+bool use_p3_mfma(const RunTarget& t, int R) {
+  return g_opt.p3_mfma && t.Atab && t.prec == DGD_FP32 && t.np == 10 && R % 16 == 0 &&
+         (double)t.E * 10.0 * (double)R < 2147483647.0;
+}
+
+void stage(const RunTarget& t, const void* us, const void* ub, void* out, int mode, double cb,
+           double cg, int R, hipStream_t st) {
+  if (use_p3_mfma(t, R)) {
+    const Shape sh = element_shape(t.E, 1, g_opt.stage_waves, g_opt.xcd_remap, g_opt.stage_grid);
+    launch_stage_p3_mfma(us, ub, out, t.elem, t.E, t.Atab, t.Ctab, t.Wtab, t.wsum, mode, cb, cg, R,
+                         sh, st);
+  } else {
+    launch_stage(t.prec == DGD_FP64 ? 0 : 1, t.np, us, ub, out, t.elem, t.E, t.S, t.N, mode, cb, cg,
+                 R, stage_shape(t.E), st);
+  }
+}
+
+// Tables of the P3 matrix-core kernel: for class (o, mask) the stacked
+// stencil matrix A = [S | N_0 | N_1 | N_2] (10 x 40, missing faces zero,
+// rows 10..15 zero), in FP32 and in the lane order of v_mfma_f32_16x16x4
+// (lane l, step s holds A[l % 16][4 s + l / 16]); C = w^T A in FP64 with
+// w the row sums of the reference mass matrix; W = w padded to 16.
+void build_p3_tables(dgd_op* op) {
+  const RefElem& R = op->ref;
+  const int np = R.np;  // 10
+  std::vector<float> At(16 * 64 * 10, 0.f);
+  std::vector<double> Ct(16 * 40, 0.0), Wt(2 * 16, 0.0);
+  double wsum = 0;
+  for (int o = 0; o < 2; ++o) {
+    std::vector<double> w(np, 0.0);
+    for (int i = 0; i < np; ++i)
+      for (int j = 0; j < np; ++j) w[i] += R.Mass[(o * np + i) * np + j];
+    for (int i = 0; i < np; ++i) Wt[o * 16 + i] = w[i];
+    if (o == 0)
+      for (double x : w) wsum += x;
+    for (int mask = 0; mask < 8; ++mask) {
+      const int cls = o * 8 + mask;
+      std::vector<double> A(16 * 40, 0.0);
+      for (int m = 0; m < np; ++m)
+        for (int k = 0; k < np; ++k) {
+          A[m * 40 + k] = R.S[((o * 8 + mask) * np + m) * np + k];
+          for (int f = 0; f < 3; ++f)
+            if (mask >> f & 1) A[m * 40 + 10 * (f + 1) + k] = R.Nb[((o * 3 + f) * np + m) * np + k];
+        }
+      for (int k = 0; k < 40; ++k) {
+        double c = 0;
+        for (int m = 0; m < np; ++m) c += w[m] * A[m * 40 + k];
+        Ct[cls * 40 + k] = c;
+      }
+      for (int l = 0; l < 64; ++l)
+        for (int s = 0; s < 10; ++s) At[(cls * 64 + l) * 10 + s] = (float)A[(l % 16) * 40 + 4 * s + l / 16];
+    }
+  }
+  op->d_Atab = (float*)upload(At);
+  op->d_Ctab = (double*)upload(Ct);
+  op->d_Wtab = (double*)upload(Wt);
+  op->wsum = wsum;
 }
 
 // Largest eigenvalue of -M^-1 A (dimensionless) by power iteration in FP64
@@ -284,17 +349,12 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
 void run_stage_steps(dgd_run* run, int64_t n, double dt) {
   const RunTarget& t = run->t;
   const double gam = dt * t.D / (t.h * t.h);
-  const Shape sh = stage_shape(t.E);
-  const int pr = t.prec == DGD_FP64 ? 0 : 1;
   for (int64_t s = 0; s < n; ++s) {
     // Shu-Osher SSP-RK3 as corrections of u^n:
     //   u1 = u + dt L u;  u2 = u + 1/4 (u1 - u) + 1/4 dt L u1;  u' = u + 2/3 (u2 - u) + 2/3 dt L u2
-    launch_stage(pr, t.np, run->U, nullptr, run->U1, t.elem, t.E, t.S, t.N, 1, 0.0, gam, run->R,
-                 sh, run->stream);
-    launch_stage(pr, t.np, run->U1, run->U, run->U2, t.elem, t.E, t.S, t.N, 1, 0.25, 0.25 * gam,
-                 run->R, sh, run->stream);
-    launch_stage(pr, t.np, run->U2, run->U, run->U, t.elem, t.E, t.S, t.N, 1, 2.0 / 3.0,
-                 2.0 / 3.0 * gam, run->R, sh, run->stream);
+    stage(t, run->U, nullptr, run->U1, 1, 0.0, gam, run->R, run->stream);
+    stage(t, run->U1, run->U, run->U2, 1, 0.25, 0.25 * gam, run->R, run->stream);
+    stage(t, run->U2, run->U, run->U, 1, 2.0 / 3.0, 2.0 / 3.0 * gam, run->R, run->stream);
   }
 }
 
@@ -464,6 +524,8 @@ int dgd_set_option(const char* name, int64_t value) {
     } else if (n == "stage_grid") {
       if (value < 0 || value > (1 << 24)) fail(DGD_EINVAL, "stage_grid must be in [0, 2^24]");
       g_opt.stage_grid = value;
+    } else if (n == "p3_mfma") {
+      g_opt.p3_mfma = value != 0;
     } else if (n == "mesh_strip") {
       if (value < 0 || value > 16384) fail(DGD_EINVAL, "mesh_strip must be in [0, 16384]");
       g_opt.mesh_strip = (int)value;
@@ -592,6 +654,7 @@ int dgd_operator_build(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, dou
       for (size_t k = 0; k < Mp.size(); ++k) Mp[k] = R.Mass[k] * h * h;
       op->d_W = (double*)upload(Wp);
       op->d_Mass = (double*)upload(Mp);
+      if (p == 3 && precision == DGD_FP32) build_p3_tables(op);
       std::vector<double> quad = build_ic_quadrature(R, kQuadN);
       op->nq = kQuadN * kQuadN;
       op->d_quad = (double*)upload(quad);
@@ -647,11 +710,9 @@ int dgd_operator_apply(dgd_op* op, const void* d_in, void* d_out, int32_t n_rhs,
     if (!op || !d_in || !d_out) fail(DGD_EINVAL, "NULL argument");
     if (n_rhs < 1) fail(DGD_EINVAL, "n_rhs must be >= 1");
     if (d_in == d_out) fail(DGD_EINVAL, "input and output must not overlap");
-    const int64_t E = op->mesh->host.n_elements();
     const double h = op->mesh->host.h;
-    launch_stage(op->precision == DGD_FP64 ? 0 : 1, op->ref.np, d_in, nullptr, d_out,
-                 op->mesh->d_elem, E, op->d_S, op->d_N, 0, 0.0, op->D / (h * h), n_rhs,
-                 stage_shape(E), (hipStream_t)hip_stream);
+    stage(plain_target(op), d_in, nullptr, d_out, 0, 0.0, op->D / (h * h), n_rhs,
+          (hipStream_t)hip_stream);
     DGD_HIP_CHECK(hipGetLastError());
     return DGD_OK;
   });
@@ -665,6 +726,9 @@ void dgd_operator_destroy(dgd_op* op) {
   (void)hipFree(op->d_W);
   (void)hipFree(op->d_Mass);
   (void)hipFree(op->d_quad);
+  (void)hipFree(op->d_Atab);
+  (void)hipFree(op->d_Ctab);
+  (void)hipFree(op->d_Wtab);
   delete op;
 }
 

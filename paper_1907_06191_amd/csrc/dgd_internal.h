@@ -82,6 +82,12 @@ struct dgd_op {
   double* d_Mass = nullptr;  // [2][np][np] FP64 physical mass
   double* d_quad = nullptr;  // [2][nq][np+3]: reference quadrature for the initial data
   int nq = 0;
+  // P3 matrix-core path (FP32 state): A operands in lane order, FP64 flux
+  // coefficients and mass-row weights (see the MFMA stage kernel)
+  float* d_Atab = nullptr;   // [16][64][10]
+  double* d_Ctab = nullptr;  // [16][40]
+  double* d_Wtab = nullptr;  // [2][16]
+  double wsum = 0;
 };
 
 namespace dgd {
@@ -103,6 +109,10 @@ struct RunTarget {
   const int* blk_geom = nullptr; // device [nblk_red] geometry of each reduction block (G > 1)
   const int* blk_start = nullptr;// device [G + 1] reduction-block range of each geometry (G > 1)
   int64_t nblk_red = 0;          // reduction blocks covering the elements
+  const float* Atab = nullptr;   // P3 matrix-core tables (NULL: VALU path only)
+  const double* Ctab = nullptr;
+  const double* Wtab = nullptr;
+  double wsum = 0;
 };
 
 }  // namespace dgd

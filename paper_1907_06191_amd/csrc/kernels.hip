@@ -161,6 +161,101 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
   }
 }
 
+// P3 stage on matrix cores (FP32 state, R a multiple of 16).  For element K
+// of class (o, mask) the contraction over the stacked stencil
+//   L(u)_K = [S_{o,mask} | N_{o,0} | N_{o,1} | N_{o,2}] (u_stencil - c)
+// is a (10 x 40) x (40 x 16) product per block of 16 right-hand sides, run
+// as ten v_mfma_f32_16x16x4_f32 steps (K = 40 = 10 x 4 exactly; rows 10..15
+// of A are zero; a missing face has zero columns).  Lane l of a step holds
+// A[m = l % 16][k = 4 s + l / 16] and B[k = 4 s + l / 16][n = l % 16] and
+// receives D[m = 4 (l / 16) + i][n = l % 16], i < 4.
+//
+// FP32 products lose mass systematically over 10^6 steps, so each column's
+// result is corrected by a constant so that its mass w^T L(u) equals the
+// FP64 sum of the face fluxes, Phi = C_{o,mask} . u_stencil, with the flux
+// coefficients C = w^T [S | N...] (w = reference mass-matrix row sums).
+// Atab: [16 classes][64 lanes][10] float; Ctab: [16][40] double;
+// Wtab: [2][16] double (row weights, zero beyond 10); wsum = sum of w.
+__global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__ us, const float* ub,
+                                                       float* out, const int4* __restrict__ elem,
+                                                       int64_t E, const float* __restrict__ Atab,
+                                                       const double* __restrict__ Ctab,
+                                                       const double* __restrict__ Wtab, double wsum,
+                                                       int mode, double cb, double cg, int R,
+                                                       int64_t nblocks, int remap) {
+  typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int q = lane >> 4, n = lane & 15;
+  const bool use_base = ub != nullptr;
+  const BlockIter it = block_iter(nblocks, remap);
+  for (int64_t b = it.first; b < it.end; b += it.stride) {
+    const int64_t e = b * (blockDim.x / WAVE) + w;
+    if (e >= E) continue;
+    const int4 m = elem[e];
+    const int o = m.w & 1;
+    const int mask = (m.w >> 1) & 7;
+    const int cls = o * 8 + mask;
+    // per-lane stencil offsets (element, node) for k = 4 s + q; the host
+    // guarantees E * 10 * R < 2^31
+    uint32_t koff[10];
+    float a[10];
+    double cf[10];
+#pragma unroll
+    for (int s = 0; s < 10; ++s) {
+      const int k = 4 * s + q;
+      const int blk = k / 10, j = k % 10;
+      int eb = (int)e;
+      if (blk == 1 && m.x >= 0) eb = m.x;
+      if (blk == 2 && m.y >= 0) eb = m.y;
+      if (blk == 3 && m.z >= 0) eb = m.z;
+      koff[s] = ((uint32_t)eb * 10u + (uint32_t)j) * (uint32_t)R + (uint32_t)n;
+      a[s] = Atab[((int64_t)cls * WAVE + lane) * 10 + s];
+      cf[s] = Ctab[cls * 40 + k];
+    }
+    double wr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) wr[i] = Wtab[o * 16 + 4 * q + i];
+    const uint32_t self = (uint32_t)e * 10u * (uint32_t)R;
+    for (int c0 = 0; c0 < R; c0 += 16) {
+      const int col = c0 + n;
+      const float c = us[self + (uint32_t)col];
+      float v[10];
+#pragma unroll
+      for (int s = 0; s < 10; ++s) v[s] = us[koff[s] + (uint32_t)c0];
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      double phi = 0.0;
+#pragma unroll
+      for (int s = 0; s < 10; ++s) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], v[s] - c, acc, 0, 0, 0);
+        phi = fma(cf[s], (double)v[s], phi);
+      }
+      double wa = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) wa = fma(wr[i], (double)acc[i], wa);
+      phi += __shfl_xor(phi, 16);
+      phi += __shfl_xor(phi, 32);
+      wa += __shfl_xor(wa, 16);
+      wa += __shfl_xor(wa, 32);
+      const double alpha = (phi - wa) / wsum;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 4 * q + i;
+        if (row >= 10) continue;
+        const uint32_t idx = self + (uint32_t)(row * R + col);
+        const double val = (double)acc[i] + alpha;
+        if (mode == 0) {
+          out[idx] = (float)(cg * val);
+        } else {
+          const double u0 = (double)us[idx];
+          const double b0 = use_base ? (double)ub[idx] : u0;
+          out[idx] = (float)(b0 + cb * (u0 - b0) + cg * val);
+        }
+      }
+    }
+  }
+}
+
 // Reduction kernels share one shape: 4 waves per workgroup, each wave walks
 // `epw` consecutive elements, lanes on right-hand sides; per-block partials
 // part[b][r][6] are summed later in a fixed order (deterministic).
@@ -482,6 +577,14 @@ void launch_stage(int prec, int np, const void* us, const void* ub, void* out, c
   } else {
     DGD_DISPATCH_NP(np, stage_t<float, NP>(us, ub, out, elem, E, S, N, mode, cb, cg, R, sh, st));
   }
+}
+
+void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4* elem, int64_t E,
+                          const float* Atab, const double* Ctab, const double* Wtab, double wsum,
+                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st) {
+  hipLaunchKernelGGL(k_stage_p3_mfma, dim3((unsigned)sh.grid), dim3(64 * sh.waves), 0, st,
+                     (const float*)us, (const float*)ub, (float*)out, elem, E, Atab, Ctab, Wtab, wsum,
+                     mode, cb, cg, R, sh.blocks, sh.remap ? 1 : 0);
 }
 
 void launch_moments(int prec, int np, const void* u, const int4* elem, int64_t E, const double* W,

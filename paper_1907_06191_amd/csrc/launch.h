@@ -30,6 +30,13 @@ void launch_stage(int prec, int np, const void* us, const void* ub, void* out, c
                   int64_t E, const void* S, const void* N, int mode, double cb, double cg, int R,
                   const Shape& sh, hipStream_t st);
 
+// P3 stage on matrix cores (FP32 state, R % 16 == 0, one element per wave:
+// the shape must have epw = 1), same modes and coefficients as
+// launch_stage, with a per-element FP64 mass correction.
+void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4* elem, int64_t E,
+                          const float* Atab, const double* Ctab, const double* Wtab, double wsum,
+                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st);
+
 // FP64 moment partial sums per logical block: part[b][r][6].  x0 is
 // [G][R][2]; blk_geom (NULL when G = 1) gives the geometry of each block.
 void launch_moments(int prec, int np, const void* u, const int4* elem, int64_t E, const double* W,
