@@ -1,6 +1,6 @@
 """Throughput of the DG diffusion hot path on one MI355X.
 
-Workload (default): the plain solve at scale -- a 100 um box on a 512 x 512
+Default workload: the plain solve at scale -- a 100 um box on a 512 x 512
 pixel grid (h = 0.1953 um), seeded random-sequential-addition disks of
 Gamma(4, mean 0.5 um) radius at packing fraction 0.6 removed as zero-flux
 axons, P2 SIPG (6 nodes per triangle), 64 start points carried together as
@@ -9,11 +9,20 @@ axons, P2 SIPG (6 nodes per triangle), 64 start points carried together as
 A "step" is one SSP-RK3 time step of the whole state (three fused stage
 launches: volume + face + lift + stage combine over every active triangle
 and every right-hand side).  The timed region advances K steps from a state
-already resident in HBM; a moment reduction (Sigma at one Delta) is timed
-separately and folded into the Sigma-solves/s figure.
+already resident in HBM.  value = GDoF-updates/s, one update advancing one
+DoF of one right-hand side by one RK3 step.
 
-Prints one JSON line (rank 0): value = GDoF-updates/s, where one update
-advances one DoF of one right-hand side by one full RK3 step.
+Also reported:
+  * Sigma-solves/s of the RK3 path, projected from the measured step time
+    and the full Delta-landing schedule;
+  * Sigma-solves/s measured end to end (initial projection, the whole
+    Delta list, moments) with the Chebyshev exponential integrator
+    (--no-expm skips it);
+  * --workload C3: the batched solve (256 uneven geometries, P1/P2 groups,
+    16 start points each); --workload C4: P3 on matrix cores, 128 start
+    points.
+
+Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -36,6 +45,14 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def schedule_steps(deltas, dt):
+    prev, n = 0.0, 0
+    for d in deltas:
+        n += max(int(np.ceil((d - prev) / dt - 1e-9)), 1)
+        prev = d
+    return n
+
+
 def cpu_baseline(g, pts, p, D, eta, sigma0, dt, lam, budget_s=20.0):
     """The FP64 oracle's SSP-RK3 on the same mesh, on a bounded sample:
     a few start points (one per worker process) for a fixed number of steps."""
@@ -45,7 +62,6 @@ def cpu_baseline(g, pts, p, D, eta, sigma0, dt, lam, budget_s=20.0):
     setup = time.time() - t0
     workers = max(1, min(8, os.cpu_count() or 1))
     sample = pts[:workers]
-    # calibrate: 3 steps, then pick a step count for ~budget_s
     t0 = time.time()
     osolve.solve(prob, sample[:1], sigma0, [3 * dt], method="rk3", dt_nom=dt, workers=1)
     per_step = (time.time() - t0) / 3
@@ -53,45 +69,49 @@ def cpu_baseline(g, pts, p, D, eta, sigma0, dt, lam, budget_s=20.0):
     t0 = time.time()
     osolve.solve(prob, sample, sigma0, [steps * dt], method="rk3", dt_nom=dt, workers=workers)
     el = time.time() - t0
-    ndof = prob.op.ndof
-    v = ndof * sample.shape[0] * steps / el / 1e9
+    v = prob.op.ndof * sample.shape[0] * steps / el / 1e9
     return {"value": v, "unit": "GDoF-updates/s", "cores": workers, "kind": "oracle",
             "sample": f"oracle SSP-RK3 (scipy CSR, FP64) on the same mesh: {sample.shape[0]} start "
                       f"points x {steps} steps, one worker process per start point, {el:.1f} s "
                       f"(+{setup:.1f} s assembly, not timed)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="C2")
-    ap.add_argument("--p", type=int, default=None, help="override polynomial degree")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="after the timed region, copy 1 GiB device-to-device once (a plain "
-                         "copy kernel of known size, to calibrate HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
+def time_steps(advance, steps, stream):
+    import torch
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    advance(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1)
 
+
+def base_record(args, value, ms_per_step, dtype, config):
+    return {
+        "metric": "DG GDoF-updates/s (and Sigma-solves/s) at 1e-4 rel err vs FP64 oracle",
+        "value": round(value, 4), "unit": "GDoF-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic (seeded RSA disk packing and start points)", "config": config,
+    }
+
+
+def plain(args):
     import torch
     from paper_1907_06191_amd import dgd
     from workloads import config, make_geometry, start_points
 
     c = config(args.workload)
     p = args.p or c["p"]
-    torch.cuda.set_device(0)
     t0 = time.time()
     g = make_geometry(c["L"], c["N"], c["geom_seed"], phi=c["phi"], n_disks=c["n_disks"])
     pts = start_points(g.disks, g.L, g.N, c["R"], np.random.default_rng(c["point_seed"]))
     log(f"geometry: {g.disks.shape[0]} disks in {time.time() - t0:.1f}s")
     mesh = dgd.Mesh(g.L, g.N, g.disks)
     info = mesh.info()
-    prec = {"fp64": dgd.DGD_FP64, "fp32": dgd.DGD_FP32}.get(c["precision"], dgd.DGD_FP32)
+    prec = dgd.DGD_FP64 if c["precision"] == "fp64" else dgd.DGD_FP32
     t0 = time.time()
     op = dgd.Operator(mesh, p, c["D"], c["eta"], prec)
     dt, lam = dgd.dgd_operator_dt(op.handle)
@@ -103,70 +123,51 @@ def main():
     stream = torch.cuda.Stream()
     ws = torch.empty(op.workspace_size(R), dtype=torch.uint8, device="cuda")
     run = dgd.Run(op, pts, c["sigma0"], workspace=ws, stream=stream)
-    # warmup (also captures the step graph)
     run.advance(args.warmup, dt)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    tw0 = time.perf_counter()
-    ev0.record(stream)
-    run.advance(args.steps, dt)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - tw0
-    gpu_ms = ev0.elapsed_time(ev1)
+    gpu_ms = time_steps(lambda k: run.advance(k, dt), args.steps, stream)
     ms_per_step = gpu_ms / args.steps
     value = dof * args.steps / (gpu_ms * 1e-3) / 1e9
-    # moment reduction cost (one Delta)
     torch.cuda.synchronize()
     tm = time.perf_counter()
     mom = run.moments(check=False)
     mom_ms = (time.perf_counter() - tm) * 1e3
-    # whole-solve projection: the Delta-landing schedule of the workload
-    prev, nsteps = 0.0, 0
-    for d in c["deltas"]:
-        n = int(np.ceil((d - prev) / dt - 1e-9))
-        nsteps += max(n, 1)
-        prev = d
+    nsteps = schedule_steps(c["deltas"], dt)
     solve_s = nsteps * ms_per_step * 1e-3 + len(c["deltas"]) * mom_ms * 1e-3
-    # roofline of the stage kernel: 32 B of FP32 state per DoF-update, 3 launches per step
     launch_ms = gpu_ms / (3 * args.steps)
-    bytes_per_launch = 32.0 / 3.0 * dof
+    sbytes = 8 if prec == dgd.DGD_FP64 else 4
+    bytes_per_launch = 8.0 * sbytes / 3.0 * dof
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
-    out = {
-        "metric": "DG GDoF-updates/s (and Sigma-solves/s) at 1e-4 rel err vs FP64 oracle",
-        "value": round(value, 4),
-        "unit": "GDoF-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64 arithmetic, f32 state" if prec == dgd.DGD_FP32 else "f64",
-        "data": "synthetic (seeded RSA disk packing and start points)",
-        "config": {
-            "workload": f"{args.workload}: plain solve, {g.N}x{g.N} grid on [0,{g.L:g}]^2 um, "
-                        f"phi={c['phi']}, P{p}, {R} start points as RHS, FP32 state",
-            "active_triangles": info["n_active"], "dof_per_rhs": info["n_active"] * npn,
-            "rhs": R, "p": p, "dt_ms": dt, "lambda_max_per_ms": lam,
-            "steps_full_solve": nsteps, "deltas_ms": [round(x, 4) for x in c["deltas"]],
-        },
-        "sigma_solves_per_s": round(R / solve_s, 6),
-        "sigma_solves_note": "projected: measured ms/step x the full Delta-landing schedule "
-                             "+ measured moment reduction per Delta",
-        "wall_s_timed": round(wall, 3),
-        "mass_after_timed": float(np.abs(mom[:, 0] - 1).max()),
-        "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"k_stage<float,{npn}>",
-            "bytes_per_launch": bytes_per_launch, "launch_ms": round(launch_ms, 5),
-        },
-    }
+    mfma = p == 3 and prec == dgd.DGD_FP32 and R % 16 == 0
+    kernel = "k_stage_p3_mfma" if mfma else f"k_stage<{'double' if sbytes == 8 else 'float'},{npn}>"
+    dtype = ("f32 MFMA contraction + f64 mass correction, f32 state" if mfma else
+             ("f64 arithmetic, f32 state" if sbytes == 4 else "f64"))
+    out = base_record(args, value, ms_per_step, dtype, {
+        "workload": f"{args.workload}: plain solve, {g.N}x{g.N} grid on [0,{g.L:g}]^2 um, "
+                    f"phi={c['phi'] if c['phi'] is not None else str(c['n_disks']) + ' disks'}, "
+                    f"P{p}, {R} start points as RHS",
+        "active_triangles": info["n_active"], "dof_per_rhs": info["n_active"] * npn, "rhs": R,
+        "p": p, "dt_ms": dt, "lambda_max_per_ms": lam, "steps_full_solve": nsteps,
+        "deltas_ms": [round(x, 4) for x in c["deltas"]]})
+    out["sigma_solves_per_s"] = round(R / solve_s, 6)
+    out["sigma_solves_note"] = ("RK3 path, projected: measured ms/step x the full Delta-landing "
+                                "schedule + measured moment reduction per Delta")
+    out["mass_after_timed"] = float(np.abs(mom[:, 0] - 1).max())
+    out["roofline"] = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+        "bytes_per_launch": bytes_per_launch, "launch_ms": round(launch_ms, 5)}
     run.close()
+    if args.expm:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sig, mom_e, napp = dgd.dgd_eap_solve_expm(op.handle, pts, c["sigma0"], c["deltas"])
+        el = time.perf_counter() - t0
+        out["expm"] = {"sigma_solves_per_s": round(R / el, 5), "seconds": round(el, 3),
+                       "operator_applications": napp,
+                       "gdof_applications_per_s": round(dof * napp / el / 1e9, 3),
+                       "note": "measured end to end: projection, whole Delta list (Chebyshev "
+                               "exponential, FP64 state), moments",
+                       "max_mass_drift": float(np.abs(mom_e[..., 0] - 1).max())}
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -179,6 +180,74 @@ def main():
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(g, pts, p, c["D"], c["eta"], c["sigma0"], dt, lam,
                                            args.cpu_budget)
+    return out
+
+
+def batched(args):
+    import torch
+    from paper_1907_06191_amd import dgd
+    from workloads import c3_workload, config
+
+    c = config("C3")
+    n = args.geoms or c["n_geoms"]
+    t0 = time.time()
+    work = c3_workload(n, workers=args.workers)
+    log(f"{n} geometries in {time.time() - t0:.0f}s")
+    meshes = [dgd.Mesh(g.L, g.N, g.disks) for g, _, _ in work]
+    ops = [dgd.Operator(m, p, c["D"], c["eta"], dgd.DGD_FP32) for m, (_, _, p) in zip(meshes, work)]
+    pts = np.stack([pp for _, pp, _ in work])
+    stream = torch.cuda.Stream()
+    b = dgd.Batch(ops, pts, c["sigma0"], stream=stream)
+    groups = b.groups()
+    R = pts.shape[1]
+    total_ms, total_updates, solve_s = 0.0, 0.0, 0.0
+    per_group = []
+    for k, gr in enumerate(groups):
+        b.advance(k, args.warmup, gr["dt"])
+        ms = time_steps(lambda s: b.advance(k, s, gr["dt"]), args.steps, stream)
+        total_ms += ms
+        total_updates += gr["dof"] * R * args.steps
+        nsteps = schedule_steps(c["deltas"], gr["dt"])
+        solve_s += nsteps * ms / args.steps * 1e-3
+        per_group.append({"p": gr["p"], "geometries": gr["size"], "dof_per_rhs": gr["dof"],
+                          "dt_ms": gr["dt"], "ms_per_step": round(ms / args.steps, 4),
+                          "gdof_updates_per_s": round(gr["dof"] * R * args.steps / (ms * 1e-3) / 1e9, 2),
+                          "steps_full_solve": nsteps})
+    mom = b.moments(check=False)
+    value = total_updates / (total_ms * 1e-3) / 1e9
+    out = base_record(args, value, total_ms / args.steps, "f64 arithmetic, f32 state", {
+        "workload": f"C3: batched solve, {n} geometries (grid edge 128..512 at h=100/512 um, "
+                    f"phi 0.4..0.7), P1/P2 groups, {R} start points each",
+        "groups": per_group})
+    out["sigma_solves_per_s"] = round(n * R / solve_s, 6)
+    out["sigma_solves_note"] = "projected: measured ms/step per group x its full schedule"
+    out["mass_after_timed"] = float(np.abs(mom[..., 0] - 1).max())
+    out["ms_per_step_note"] = "sum over groups of one RK3 step of every geometry in the group"
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4"])
+    ap.add_argument("--p", type=int, default=None, help="override polynomial degree")
+    ap.add_argument("--geoms", type=int, default=0, help="C3: number of geometries (default all)")
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-expm", dest="expm", action="store_false")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, copy 1 GiB device-to-device once (a plain "
+                         "copy kernel of known size, to calibrate HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    out = batched(args) if args.workload == "C3" else plain(args)
     print(json.dumps(out), flush=True)
 
 

@@ -185,6 +185,24 @@ int dgd_eap_solve(dgd_op* op, const double* points, int32_t n_points, double sig
                   double* moments_out, void* d_ws, size_t ws_bytes, void* hip_stream);
 
 /*
+ * Whole solve with the exact semi-discrete flow instead of SSP-RK3: for each
+ * interval of the Delta list, u <- exp((Delta_k - Delta_{k-1}) L) u by a
+ * Chebyshev expansion on the spectrum [-b, 0] of L = -M^-1 A (Tal-Ezer and
+ * Kosloff), the series cut where its remaining coefficients sum below
+ * 1e-17.  About 9 sqrt(b (Delta_k - Delta_{k-1}) / 2) operator applications
+ * per interval instead of (Delta_k - Delta_{k-1}) / dt RK3 steps.  The
+ * state is FP64 whatever the op's precision.
+ *   lambda_bound: b, which must bound the largest eigenvalue of M^-1 A;
+ *                 <= 0 uses 1.05 x the device power-iteration estimate.
+ *   n_applies: NULL or the number of operator applications made.
+ * Outputs and errors as dgd_eap_solve (the library allocates, null stream
+ * of its own).
+ */
+int dgd_eap_solve_expm(dgd_op* op, const double* points, int32_t n_points, double sigma0_um,
+                       const double* deltas_ms, int32_t n_deltas, double lambda_bound,
+                       double* sigma_out, double* moments_out, int64_t* n_applies);
+
+/*
  * Batched solve (section 4.1 over many substrates; the paper's timing table
  * runs 37 start points one after another): n_geoms operators, each on its
  * own mesh, with n_points start points each.  The operators must share h,

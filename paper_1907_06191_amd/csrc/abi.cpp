@@ -448,6 +448,40 @@ std::vector<std::pair<int64_t, double>> schedule(const double* deltas, int n, do
   return s;
 }
 
+// Coefficients c_k = e^-z I_k(z) (times 2 for k >= 1) of
+// exp(t L) = sum_k c_k T_k(I + 2 L / b), z = t b / 2, by Miller's backward
+// recurrence I_{k-1} = (2k / z) I_k + I_{k+1} normalised with
+// I_0 + 2 sum_{k>=1} I_k = e^z; cut where the tail falls below 1e-17
+// (the c_k sum to 1).
+std::vector<double> cheb_coefficients(double z) {
+  if (!(z > 0)) return {1.0};
+  int K = (int)std::ceil(12.0 * std::sqrt(z) + 60.0);
+  const int start = K + 40;
+  std::vector<double> I(start + 2, 0.0);
+  I[start + 1] = 0.0;
+  I[start] = 1e-300;
+  for (int k = start; k >= 1; --k) {
+    I[k - 1] = (2.0 * k / z) * I[k] + I[k + 1];
+    if (I[k - 1] > 1e250)
+      for (int j = k - 1; j <= start; ++j) I[j] *= 1e-250;
+  }
+  double S = I[0];
+  for (int k = 1; k <= start; ++k) S += 2.0 * I[k];
+  std::vector<double> c(start + 1);
+  for (int k = 0; k <= start; ++k) c[k] = (k == 0 ? 1.0 : 2.0) * I[k] / S;
+  double tail = 0;
+  int last = start;
+  for (int k = start; k >= 0; --k) {
+    tail += c[k];
+    if (tail > 1e-17) {
+      last = k;
+      break;
+    }
+  }
+  c.resize(std::max(last + 1, 2));
+  return c;
+}
+
 // ------------------------------------------------------------- batches ----
 
 void batch_destroy(dgd_batch* b) {
@@ -825,6 +859,78 @@ int dgd_eap_solve(dgd_op* op, const double* points, int32_t n_points, double sig
     return DGD_OK;
   });
   dgd_run_destroy(run);
+  return rc;
+}
+
+int dgd_eap_solve_expm(dgd_op* op, const double* points, int32_t n_points, double sigma0_um,
+                       const double* deltas_ms, int32_t n_deltas, double lambda_bound,
+                       double* sigma_out, double* moments_out, int64_t* n_applies) {
+  dgd_run* run = nullptr;
+  double* buf = nullptr;
+  int rc = guarded([&]() -> int {
+    if (!op || !points || !deltas_ms || !sigma_out) fail(DGD_EINVAL, "NULL argument");
+    if (n_points < 1 || n_deltas < 1) fail(DGD_EINVAL, "bad counts");
+    if (!(sigma0_um > 0)) fail(DGD_EINVAL, "sigma0 must be positive");
+    schedule(deltas_ms, n_deltas, 1.0);  // validates the list
+    check_points(op->mesh->host, points, n_points);
+    double b = lambda_bound;
+    if (!(b > 0)) {
+      double lam = op->lambda_max;
+      if (!(lam > 0)) lam = power_lambda(op, 400) * op->D / (op->mesh->host.h * op->mesh->host.h);
+      b = 1.05 * lam;
+    }
+    RunTarget t = plain_target(op);
+    t.prec = DGD_FP64;           // the recurrence runs on an FP64 state
+    t.Atab = nullptr;
+    run = run_create(t, points, n_points, sigma0_um, nullptr, 0, nullptr);
+    const int64_t n = t.E * t.np * (int64_t)n_points;
+    DGD_HIP_CHECK(hipMalloc(&buf, (size_t)n * sizeof(double)));
+    double* res = (double*)run->U;   // u, then the running sum
+    double* T[3] = {(double*)run->U1, (double*)run->U2, buf};
+    const Shape sh = stage_shape(t.E);
+    const double cg = 2.0 * t.D / (b * t.h * t.h);    // X = I + (2 / b) L, L = (D / h^2) Lhat
+    int64_t applies = 0;
+    std::vector<double> mom((size_t)n_points * 6);
+    int status = DGD_OK;
+    std::string why;
+    double prev = 0;
+    for (int kd = 0; kd < n_deltas && status == DGD_OK; ++kd) {
+      const std::vector<double> c = cheb_coefficients(0.5 * b * (deltas_ms[kd] - prev));
+      prev = deltas_ms[kd];
+      // T0 = u; T_{-1} = X T0 (so that T1 = 2 X T0 - T_{-1} = X T0); res = c0 T0
+      launch_axpby(T[0], res, 1.0, 0.0, n, run->stream);
+      launch_stage(0, t.np, T[0], nullptr, T[2], t.elem, t.E, t.S, t.N, 1, 0.0, cg, n_points, sh,
+                   run->stream);
+      launch_axpby(res, T[0], c[0], 0.0, n, run->stream);
+      applies += 1;
+      int cur = 0, prv = 2;
+      for (size_t k = 1; k < c.size(); ++k) {
+        const int nxt = 3 - cur - prv;
+        launch_cheb(t.np, T[cur], T[prv], T[nxt], res, t.elem, t.E, t.S, t.N, cg, c[k], n_points, sh,
+                    run->stream);
+        prv = cur;
+        cur = nxt;
+        ++applies;
+      }
+      DGD_HIP_CHECK(hipGetLastError());
+      const int mrc = run_moments(run, mom.data(), &why);
+      for (int r = 0; r < n_points; ++r) {
+        const double* m = &mom[(size_t)r * 6];
+        double* s = &sigma_out[((size_t)r * n_deltas + kd) * 3];
+        s[0] = m[3] / m[0];
+        s[1] = m[4] / m[0];
+        s[2] = m[5] / m[0];
+        if (moments_out)
+          std::memcpy(&moments_out[((size_t)r * n_deltas + kd) * 6], m, 6 * sizeof(double));
+      }
+      if (mrc) status = mrc;
+    }
+    if (n_applies) *n_applies = applies;
+    if (status) fail(status, why);
+    return DGD_OK;
+  });
+  if (run) run_destroy(run);
+  if (buf) (void)hipFree(buf);
   return rc;
 }
 

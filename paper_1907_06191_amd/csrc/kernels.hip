@@ -70,13 +70,16 @@ __device__ inline BlockIter block_iter(int64_t nblocks, int remap) {
 // 10^6 steps of a solve; with packed FP32 off, gfx950 issues FP64 and FP32
 // FMAs at the same rate, so the FP64 arithmetic costs no VALU throughput
 // and the HBM traffic is that of the FP32 state.
+//
+// mode 2 (Chebyshev recurrence of exp(t L), see launch_cheb):
+//   out = 2 (us + cg L(us)) - ub,  res += ck * out.
 template <typename TS, int NP>
 __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const TS* ub, TS* out,
                                                const int4* __restrict__ elem, int64_t E,
                                                const double* __restrict__ S,
                                                const double* __restrict__ Nm, int mode, double cb,
                                                double cg, int R, int epw, int64_t nblocks,
-                                               int remap) {
+                                               int remap, TS* res = nullptr, double ck = 0.0) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   // right-hand sides: 64 per wave, chunk blockIdx.y; lanes past R load a
@@ -146,6 +149,13 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
       if (mode == 0) {
 #pragma unroll
         for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)(cg * acc[i]);
+      } else if (mode == 2) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          const double t = 2.0 * ((double)su[i] + cg * acc[i]) - (double)sb[i];
+          out[self + (int64_t)i * R] = (TS)t;
+          res[self + (int64_t)i * R] = (TS)((double)res[self + (int64_t)i * R] + ck * t);
+        }
       } else if (use_base) {
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
@@ -525,6 +535,13 @@ __global__ void __launch_bounds__(256) k_dot_mass(const double* __restrict__ x,
   }
 }
 
+// y = a x + b y (b == 0 never reads y)
+__global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, double a, double b,
+                        int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
+}
+
 __global__ void k_fill_random(double* x, int64_t n, uint64_t seed) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -585,6 +602,20 @@ void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4*
   hipLaunchKernelGGL(k_stage_p3_mfma, dim3((unsigned)sh.grid), dim3(64 * sh.waves), 0, st,
                      (const float*)us, (const float*)ub, (float*)out, elem, E, Atab, Ctab, Wtab, wsum,
                      mode, cb, cg, R, sh.blocks, sh.remap ? 1 : 0);
+}
+
+void launch_cheb(int np, const double* tcur, const double* tprev, double* tnext, double* res,
+                 const int4* elem, int64_t E, const void* S, const void* N, double cg, double ck,
+                 int R, const Shape& sh, hipStream_t st) {
+  const unsigned chunks = (unsigned)((R + 63) / 64);
+  DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage<double, NP>), dim3((unsigned)sh.grid, chunks),
+                                         dim3(64 * sh.waves), 0, st, tcur, tprev, tnext, elem, E,
+                                         (const double*)S, (const double*)N, 2, 0.0, cg, R, sh.epw,
+                                         sh.blocks, sh.remap ? 1 : 0, res, ck));
+}
+
+void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t st) {
+  k_axpby<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(y, x, a, b, n);
 }
 
 void launch_moments(int prec, int np, const void* u, const int4* elem, int64_t E, const double* W,

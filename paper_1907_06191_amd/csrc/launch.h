@@ -37,6 +37,14 @@ void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4*
                           const float* Atab, const double* Ctab, const double* Wtab, double wsum,
                           int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st);
 
+// One step of the Chebyshev recurrence for exp(t L) (FP64 state):
+//   tnext = 2 (tcur + cg L(tcur)) - tprev,   res += ck * tnext.
+void launch_cheb(int np, const double* tcur, const double* tprev, double* tnext, double* res,
+                 const int4* elem, int64_t E, const void* S, const void* N, double cg, double ck,
+                 int R, const Shape& sh, hipStream_t st);
+// y = a x + b y over n values (b == 0: y is only written).
+void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t st);
+
 // FP64 moment partial sums per logical block: part[b][r][6].  x0 is
 // [G][R][2]; blk_geom (NULL when G = 1) gives the geometry of each block.
 void launch_moments(int prec, int np, const void* u, const int4* elem, int64_t E, const double* W,

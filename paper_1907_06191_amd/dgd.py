@@ -91,6 +91,8 @@ _sig("dgd_surrogate_train", [_vp, _vp, _c_dp, _c_dp, ctypes.c_int32, ctypes.c_in
                              ctypes.c_double, ctypes.c_uint64, _c_dp])
 _sig("dgd_surrogate_predict", [_vp, _vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, _c_dp, _vp])
 _sig("dgd_surrogate_destroy", [_vp], None)
+_sig("dgd_eap_solve_expm", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, ctypes.c_int32,
+                            ctypes.c_double, _c_dp, _c_dp, ctypes.POINTER(ctypes.c_int64)])
 _sig("dgd_eap_solve", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, ctypes.c_int32, _c_dp,
                        _c_dp, _vp, ctypes.c_size_t, _vp])
 
@@ -327,6 +329,19 @@ def dgd_surrogate_destroy(s) -> None:
 def _op_array(ops):
     handles = [o.handle if hasattr(o, "handle") else o for o in ops]
     return (_vp * len(handles))(*handles)
+
+
+def dgd_eap_solve_expm(op, points, sigma0: float, deltas, lambda_bound: float = 0.0):
+    """Returns (sigma [n][nDelta][3], moments [n][nDelta][6], operator applications)."""
+    pts = _f64(points, (2,))
+    d = _f64(deltas).ravel()
+    n = pts.shape[0]
+    sig = np.zeros((n, d.size, 3))
+    mom = np.zeros((n, d.size, 6))
+    na = ctypes.c_int64()
+    _check(_lib.dgd_eap_solve_expm(op, _ptr(pts), n, float(sigma0), _ptr(d), int(d.size), float(lambda_bound),
+                                   _ptr(sig), _ptr(mom), ctypes.byref(na)))
+    return sig, mom, na.value
 
 
 def dgd_batch_workspace_size(ops, n_points: int) -> int:

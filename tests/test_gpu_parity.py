@@ -300,3 +300,21 @@ def test_p3_mfma_solve_matches_valu_and_oracle(dgd):
     say(f"  mfma vs oracle {e_ref:.2e}, vs valu {e_valu:.2e}, |M0-1| {drift:.2e}")
     assert e_ref < 1e-4 and e_valu < 1e-4
     assert drift < 1e-6
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_expm_solve_matches_oracle_flow(dgd, p):
+    """Chebyshev exponential on the GPU (FP64 state) against the oracle's
+    Chebyshev exponential: both are the exact semi-discrete flow, so Sigma
+    agrees to 1e-10 whatever the spectral bounds each side uses."""
+    g, pts = _small_dense_case(nrhs=4, N=32, seed=31 + p)
+    deltas = [0.2, 1.0, 3.0]
+    prob = osolve.prepare(g.L, g.N, g.disks, p, 2.0, 10.0)
+    ref = osolve.solve(prob, pts, 0.3, deltas, method="cheb")
+    mesh = dgd.Mesh(g.L, g.N, g.disks)
+    op = dgd.Operator(mesh, p, 2.0, 10.0, dgd.DGD_FP32)
+    sig, mom, napp = dgd.dgd_eap_solve_expm(op.handle, pts, 0.3, deltas)
+    err = omom.rel_err(sig, omom.sigma_a(ref)).max()
+    say(f"expm p={p}: {napp} applications, max rel err vs oracle {err:.2e}, |M0-1| "
+        f"{np.abs(mom[..., 0] - 1).max():.1e}")
+    assert err < 1e-10
