@@ -122,7 +122,7 @@ def plain(args):
     dof = info["n_active"] * npn * R
     stream = torch.cuda.Stream()
     ws = torch.empty(op.workspace_size(R), dtype=torch.uint8, device="cuda")
-    run = dgd.Run(op, pts, c["sigma0"], workspace=ws, stream=stream)
+    run = dgd.Run(op, pts, c["sigma0"], workspace=ws, stream=stream)   # tunes the stage shape
     run.advance(args.warmup, dt)
     gpu_ms = time_steps(lambda k: run.advance(k, dt), args.steps, stream)
     ms_per_step = gpu_ms / args.steps
@@ -148,6 +148,7 @@ def plain(args):
         "active_triangles": info["n_active"], "dof_per_rhs": info["n_active"] * npn, "rhs": R,
         "p": p, "dt_ms": dt, "lambda_max_per_ms": lam, "steps_full_solve": nsteps,
         "deltas_ms": [round(x, 4) for x in c["deltas"]]})
+    out["stage_shape_table"] = dgd.dgd_tune_export().strip().split("\n")
     out["sigma_solves_per_s"] = round(R / solve_s, 6)
     out["sigma_solves_note"] = ("RK3 path, projected: measured ms/step x the full Delta-landing "
                                 "schedule + measured moment reduction per Delta")
@@ -219,6 +220,7 @@ def batched(args):
         "workload": f"C3: batched solve, {n} geometries (grid edge 128..512 at h=100/512 um, "
                     f"phi 0.4..0.7), P1/P2 groups, {R} start points each",
         "groups": per_group})
+    out["stage_shape_table"] = dgd.dgd_tune_export().strip().split("\n")
     out["sigma_solves_per_s"] = round(n * R / solve_s, 6)
     out["sigma_solves_note"] = "projected: measured ms/step per group x its full schedule"
     out["mass_after_timed"] = float(np.abs(mom[..., 0] - 1).max())
@@ -238,6 +240,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-expm", dest="expm", action="store_false")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--tune-file", default=None,
+                    help="stage launch-shape table: merged in before the runs if the file "
+                         "exists, written back after them (a run with a warm file does no tuning)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 1 GiB device-to-device once (a plain "
                          "copy kernel of known size, to calibrate HBM byte counters)")
@@ -247,7 +252,14 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    from paper_1907_06191_amd import dgd
+    if args.tune_file and os.path.exists(args.tune_file):
+        with open(args.tune_file) as f:
+            dgd.dgd_tune_import(f.read())
     out = batched(args) if args.workload == "C3" else plain(args)
+    if args.tune_file:
+        with open(args.tune_file, "w") as f:
+            f.write(dgd.dgd_tune_export())
     print(json.dumps(out), flush=True)
 
 

@@ -294,8 +294,43 @@ void dgd_surrogate_destroy(dgd_surrogate* s);
  *                  right-hand-side count is a multiple of 16
  *   "mesh_strip"   element order of meshes created afterwards: vertical strips
  *                  of this many cell columns, each row-major (0 = plain rows)
+ *   "autotune"     1 (default) = runs take the tuned stage launch shape of
+ *                  their key, tuning it when the run is created if the key
+ *                  is new; 0 = the shape options above
  * Errors: EINVAL for an unknown name or a value out of range. */
 int dgd_set_option(const char* name, int64_t value);
+
+/*
+ * Launch-shape autotuner of the stage kernel (the per-stage update of the
+ * time loop, section 3.2).  Every launch shape gives the same bits, so the
+ * choice only sets the speed.  The search space: elements per wave {1, 2,
+ * 4} (1 for the P3 matrix-core kernel), waves per workgroup {1, 2, 4},
+ * XCD-banded block order on/off, and a persistent grid of {4, 8, 16}
+ * workgroups per compute unit or none.  After a 30 ms warm-up, each shape
+ * is timed with HIP events over about 2 ms of launches of the two-input
+ * stage (stage input and base state read, output written), twice, in
+ * forward and reverse order, and the best four once more; the fastest is
+ * stored in a process-wide table under the key
+ * (architecture, Np, state precision, kernel, right-hand sides, floor of
+ * log2 of the element count).
+ *
+ * dgd_autotune tunes op at n_points right-hand sides on hip_stream (NULL:
+ * the null stream), allocating three state buffers for the trial; shape_out
+ * (nullable) [4] = (elements per wave, waves, XCD order, workgroups per CU
+ * or 0), ms_out (nullable) = the best time of one stage launch.
+ * Synchronous.  Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+int dgd_autotune(dgd_op* op, int32_t n_points, void* hip_stream, int32_t* shape_out,
+                 double* ms_out);
+/* The table as text, one line per key: "key epw waves xcd grid_per_cu ms".
+ * len_out (nullable) = bytes needed including the terminating NUL; buf may
+ * be NULL to query the size, else cap must hold them (EINVAL otherwise). */
+int dgd_tune_export(char* buf, size_t cap, size_t* len_out);
+/* Merge lines in the export format into the table (EINVAL on a bad line:
+ * nothing is merged then).  Lines starting with '#' are skipped. */
+int dgd_tune_import(const char* text);
+/* Empty the table. */
+void dgd_tune_clear(void);
 
 #ifdef __cplusplus
 }

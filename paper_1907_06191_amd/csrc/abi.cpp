@@ -17,6 +17,7 @@
 
 #include "dgd_internal.h"
 #include "launch.h"
+#include "tune.h"
 
 namespace dgd {
 
@@ -39,6 +40,7 @@ struct Options {
   int64_t stage_grid = 0;   // > 0: persistent stage kernel with this many workgroups
   int mesh_strip = 64;      // element order: vertical strips of this many cell columns (0: rows)
   bool p3_mfma = true;      // P3 FP32 stages on matrix cores when R % 16 == 0
+  bool autotune = true;     // tune the stage launch shape per key on first use
 };
 Options g_opt;
 
@@ -138,15 +140,26 @@ bool use_p3_mfma(const RunTarget& t, int R) {
          (double)t.E * 10.0 * (double)R < 2147483647.0;
 }
 
-void stage(const RunTarget& t, const void* us, const void* ub, void* out, int mode, double cb,
-           double cg, int R, hipStream_t st) {
+// Launch shape of the stage kernel on (t, R): the tuned one for its key
+// when autotuning is on and the key has been tuned, else the options.
+Shape pick_shape(const RunTarget& t, int R) {
+  const bool mfma = use_p3_mfma(t, R);
+  if (g_opt.autotune) {
+    TuneParams p;
+    if (tune_find(tune_key(t.np, t.prec, mfma, R, t.E), &p)) return tune_shape(p, t.E);
+  }
+  return element_shape(t.E, mfma ? 1 : g_opt.stage_epw, g_opt.stage_waves, g_opt.xcd_remap,
+                       g_opt.stage_grid);
+}
+
+void stage(const RunTarget& t, const Shape& sh, const void* us, const void* ub, void* out, int mode,
+           double cb, double cg, int R, hipStream_t st) {
   if (use_p3_mfma(t, R)) {
-    const Shape sh = element_shape(t.E, 1, g_opt.stage_waves, g_opt.xcd_remap, g_opt.stage_grid);
     launch_stage_p3_mfma(us, ub, out, t.elem, t.E, t.Atab, t.Ctab, t.Wtab, t.wsum, mode, cb, cg, R,
                          sh, st);
   } else {
     launch_stage(t.prec == DGD_FP64 ? 0 : 1, t.np, us, ub, out, t.elem, t.E, t.S, t.N, mode, cb, cg,
-                 R, stage_shape(t.E), st);
+                 R, sh, st);
   }
 }
 
@@ -324,6 +337,14 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
     }
     DGD_HIP_CHECK(hipMemcpyAsync(run->d_x0, run->x0.data(), run->x0.size() * sizeof(double),
                                  hipMemcpyHostToDevice, run->stream));
+    // the stage launch shape, tuned on first use of its key (the two stage
+    // buffers are free until the first step)
+    if (g_opt.autotune) {
+      TuneParams p;
+      if (!tune_find(tune_key(t.np, t.prec, use_p3_mfma(t, R), R, t.E), &p))
+        tune_stage(t, R, use_p3_mfma(t, R), run->U1, run->U2, run->U, run->stream);
+    }
+    run->sh = pick_shape(t, R);
     const Shape shr = reduce_shape(t.E);
     launch_ic_mass(t.np, t.elem, t.E, t.quad, t.nq, run->d_x0, t.blk_geom, sigma0, t.h, kCutoff, R,
                    shr, run->d_part, run->stream);
@@ -352,9 +373,9 @@ void run_stage_steps(dgd_run* run, int64_t n, double dt) {
   for (int64_t s = 0; s < n; ++s) {
     // Shu-Osher SSP-RK3 as corrections of u^n:
     //   u1 = u + dt L u;  u2 = u + 1/4 (u1 - u) + 1/4 dt L u1;  u' = u + 2/3 (u2 - u) + 2/3 dt L u2
-    stage(t, run->U, nullptr, run->U1, 1, 0.0, gam, run->R, run->stream);
-    stage(t, run->U1, run->U, run->U2, 1, 0.25, 0.25 * gam, run->R, run->stream);
-    stage(t, run->U2, run->U, run->U, 1, 2.0 / 3.0, 2.0 / 3.0 * gam, run->R, run->stream);
+    stage(t, run->sh, run->U, nullptr, run->U1, 1, 0.0, gam, run->R, run->stream);
+    stage(t, run->sh, run->U1, run->U, run->U2, 1, 0.25, 0.25 * gam, run->R, run->stream);
+    stage(t, run->sh, run->U2, run->U, run->U, 1, 2.0 / 3.0, 2.0 / 3.0 * gam, run->R, run->stream);
   }
 }
 
@@ -563,10 +584,68 @@ int dgd_set_option(const char* name, int64_t value) {
     } else if (n == "mesh_strip") {
       if (value < 0 || value > 16384) fail(DGD_EINVAL, "mesh_strip must be in [0, 16384]");
       g_opt.mesh_strip = (int)value;
+    } else if (n == "autotune") {
+      g_opt.autotune = value != 0;
     } else fail(DGD_EINVAL, "unknown option " + n);
     return DGD_OK;
   });
 }
+
+int dgd_autotune(dgd_op* op, int32_t n_points, void* hip_stream, int32_t* shape_out,
+                 double* ms_out) {
+  void* a = nullptr;
+  void* b = nullptr;
+  void* c = nullptr;
+  int rc = guarded([&]() -> int {
+    if (!op) fail(DGD_EINVAL, "op is NULL");
+    if (n_points < 1) fail(DGD_EINVAL, "n_points must be >= 1");
+    const RunTarget t = plain_target(op);
+    const size_t bytes = (size_t)t.E * t.np * n_points * state_bytes(t.prec);
+    DGD_HIP_CHECK(hipMalloc(&a, bytes));
+    DGD_HIP_CHECK(hipMalloc(&b, bytes));
+    DGD_HIP_CHECK(hipMalloc(&c, bytes));
+    const int64_t n = (int64_t)(bytes / state_bytes(t.prec));
+    if (t.prec == DGD_FP64)
+      launch_fill_random((double*)c, n, 0xba5eull, (hipStream_t)hip_stream);
+    else
+      launch_fill_random_f32((float*)c, n, 0xba5eull, (hipStream_t)hip_stream);
+    const TuneParams p = tune_stage(t, n_points, use_p3_mfma(t, n_points), a, b, c,
+                                    (hipStream_t)hip_stream);
+    if (shape_out) {
+      shape_out[0] = p.epw;
+      shape_out[1] = p.waves;
+      shape_out[2] = p.remap;
+      shape_out[3] = p.grid_per_cu;
+    }
+    if (ms_out) *ms_out = p.ms;
+    return DGD_OK;
+  });
+  (void)hipFree(a);
+  (void)hipFree(b);
+  (void)hipFree(c);
+  return rc;
+}
+
+int dgd_tune_export(char* buf, size_t cap, size_t* len_out) {
+  return guarded([&]() -> int {
+    const std::string s = tune_export();
+    if (len_out) *len_out = s.size() + 1;
+    if (buf) {
+      if (cap < s.size() + 1) fail(DGD_EINVAL, "buffer smaller than the table");
+      std::memcpy(buf, s.c_str(), s.size() + 1);
+    }
+    return DGD_OK;
+  });
+}
+
+int dgd_tune_import(const char* text) {
+  return guarded([&]() -> int {
+    if (!text) fail(DGD_EINVAL, "text is NULL");
+    return tune_import(text) >= 0 ? DGD_OK : DGD_EINVAL;
+  });
+}
+
+void dgd_tune_clear(void) { tune_clear(); }
 
 int dgd_mesh_create(double L_um, int32_t n_cells, const double* disks, int32_t n_disks,
                     dgd_mesh** out) {
@@ -745,7 +824,8 @@ int dgd_operator_apply(dgd_op* op, const void* d_in, void* d_out, int32_t n_rhs,
     if (n_rhs < 1) fail(DGD_EINVAL, "n_rhs must be >= 1");
     if (d_in == d_out) fail(DGD_EINVAL, "input and output must not overlap");
     const double h = op->mesh->host.h;
-    stage(plain_target(op), d_in, nullptr, d_out, 0, 0.0, op->D / (h * h), n_rhs,
+    const RunTarget t = plain_target(op);
+    stage(t, pick_shape(t, n_rhs), d_in, nullptr, d_out, 0, 0.0, op->D / (h * h), n_rhs,
           (hipStream_t)hip_stream);
     DGD_HIP_CHECK(hipGetLastError());
     return DGD_OK;
@@ -887,7 +967,7 @@ int dgd_eap_solve_expm(dgd_op* op, const double* points, int32_t n_points, doubl
     DGD_HIP_CHECK(hipMalloc(&buf, (size_t)n * sizeof(double)));
     double* res = (double*)run->U;   // u, then the running sum
     double* T[3] = {(double*)run->U1, (double*)run->U2, buf};
-    const Shape sh = stage_shape(t.E);
+    const Shape sh = run->sh;
     const double cg = 2.0 * t.D / (b * t.h * t.h);    // X = I + (2 / b) L, L = (D / h^2) Lhat
     int64_t applies = 0;
     std::vector<double> mom((size_t)n_points * 6);

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/dgd.h"
+#include "launch.h"
 
 namespace dgd {
 
@@ -132,6 +133,7 @@ struct dgd_run {
   double* d_part = nullptr;   // [nblk_red][R][6] partial sums
   double* d_mom = nullptr;    // [G][R][6]
   int* d_blk_start = nullptr; // [G + 1] (plain runs: {0, nblk_red})
+  dgd::Shape sh;              // stage launch shape
   std::vector<double> x0;
   double t_ms = 0;
   // captured step graphs keyed by (dt bits, steps)

@@ -55,6 +55,46 @@ __device__ inline BlockIter block_iter(int64_t nblocks, int remap) {
   return it;
 }
 
+// Stochastic rounding of an FP64 value to FP32: the FP32 neighbour below
+// or above v in magnitude, the upper one with probability equal to the
+// fraction of an FP32 ulp that v lies above the lower one, so the rounding
+// error has zero mean.  Rounding every stored state to nearest loses
+// increments below half an ulp the same way every step (the state then
+// drifts, mass included, over 10^5 - 10^6 steps); with stochastic rounding
+// the error is a zero-mean random walk.
+//
+// For v in the FP32 normal range the low 29 of the 52 FP64 mantissa bits
+// are that fraction: adding a uniform 29-bit integer r to the magnitude bits
+// and clearing those 29 bits carries into the kept part with probability
+// fraction / 2^29 (a carry into the exponent is the correct next binade),
+// and the result converts to FP32 exactly.  r hashes the kept bits with a
+// salt from the element's cell, orientation and face mask and the (node,
+// right-hand side) slot: independent of the fraction, deterministic, and
+// the same whether a geometry is solved alone or inside a batch.  Outside
+// the FP32 normal range (zero, |v| < 2^-126 where an FP32 ulp is fixed, or
+// |v| >= 2^127) the value rounds to nearest.
+__device__ __forceinline__ float round_stochastic(double v, uint32_t salt) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t hi = (uint32_t)(b >> 32);
+  const uint32_t ex = (hi >> 20) & 0x7ffu;           // biased FP64 exponent
+  uint32_t r = hi ^ ((uint32_t)b >> 29) ^ salt;
+  r *= 0x9E3779B1u;
+  r ^= r >> 16;
+  r *= 0x85EBCA77u;
+  r ^= r >> 13;
+  const uint64_t t = (b + (uint64_t)(r >> 3)) & ~0x1fffffffull;
+  const float sr = (float)__longlong_as_double((long long)t);
+  return ex - 897u <= 252u ? sr : (float)v;          // 2^-126 <= |v| < 2^127
+}
+
+__device__ __forceinline__ uint32_t state_salt(int meta, int slot) {
+  return (uint32_t)meta ^ ((uint32_t)slot * 0x85EBCA6Bu);
+}
+__device__ __forceinline__ void store_state(float* p, int64_t i, double v, uint32_t salt) {
+  p[i] = round_stochastic(v, salt);
+}
+__device__ __forceinline__ void store_state(double* p, int64_t i, double v, uint32_t) { p[i] = v; }
+
 // mode 0 (operator apply):  out = cg * L(us)
 // mode 1 (SSP-RK3 stage):    out = base + cb * (us - base) + cg * L(us),
 //                            base = ub when given, else us.
@@ -160,12 +200,14 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
           const double b0 = (double)sb[i];
-          out[self + (int64_t)i * R] = (TS)(b0 + cb * ((double)su[i] - b0) + cg * acc[i]);
+          store_state(out, self + (int64_t)i * R, b0 + cb * ((double)su[i] - b0) + cg * acc[i],
+                      state_salt(m.w, i * R + r));
         }
       } else {
 #pragma unroll
         for (int i = 0; i < NP; ++i)
-          out[self + (int64_t)i * R] = (TS)((double)su[i] + cg * acc[i]);
+          store_state(out, self + (int64_t)i * R, (double)su[i] + cg * acc[i],
+                      state_salt(m.w, i * R + r));
       }
     }
   }
@@ -259,7 +301,8 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
         } else {
           const double u0 = (double)us[idx];
           const double b0 = use_base ? (double)ub[idx] : u0;
-          out[idx] = (float)(b0 + cb * (u0 - b0) + cg * val);
+          out[idx] = round_stochastic(b0 + cb * (u0 - b0) + cg * val,
+                                      state_salt(m.w, row * R + col));
         }
       }
     }
@@ -542,7 +585,8 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, do
   if (i < n) y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
 }
 
-__global__ void k_fill_random(double* x, int64_t n, uint64_t seed) {
+template <typename T>
+__global__ void k_fill_random(T* x, int64_t n, uint64_t seed) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   // splitmix64 of (seed, i)
@@ -550,7 +594,7 @@ __global__ void k_fill_random(double* x, int64_t n, uint64_t seed) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   z ^= z >> 31;
-  x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  x[i] = (T)((double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0);
 }
 
 template <typename T, int NP>
@@ -669,7 +713,13 @@ void launch_dot_mass(int np, const double* x, const double* y, const int4* elem,
 }
 
 void launch_fill_random(double* x, int64_t n, uint64_t seed, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill_random, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, seed);
+  hipLaunchKernelGGL(k_fill_random<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n,
+                     seed);
+}
+
+void launch_fill_random_f32(float* x, int64_t n, uint64_t seed, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_random<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n,
+                     seed);
 }
 
 }  // namespace dgd

@@ -73,5 +73,6 @@ void launch_dot_mass(int np, const double* x, const double* y, const int4* elem,
 
 // x[i] = deterministic pseudo-random value in [-1, 1) from (seed, i).
 void launch_fill_random(double* x, int64_t n, uint64_t seed, hipStream_t st);
+void launch_fill_random_f32(float* x, int64_t n, uint64_t seed, hipStream_t st);
 
 }  // namespace dgd

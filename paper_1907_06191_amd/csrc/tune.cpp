@@ -1,0 +1,197 @@
+// Launch-shape autotuner of the stage kernels.
+#include "tune.h"
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <sstream>
+#include <vector>
+
+namespace dgd {
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, TuneParams> g_table;
+
+struct DeviceInfo {
+  std::string arch;
+  int cus = 0;
+};
+
+DeviceInfo device_info() {
+  int dev = 0;
+  DGD_HIP_CHECK(hipGetDevice(&dev));
+  static std::mutex mu;
+  static std::map<int, DeviceInfo> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  hipDeviceProp_t prop;
+  DGD_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+  DeviceInfo d;
+  d.arch = prop.gcnArchName;
+  const size_t colon = d.arch.find(':');
+  if (colon != std::string::npos) d.arch.resize(colon);
+  DGD_HIP_CHECK(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev));
+  cache[dev] = d;
+  return d;
+}
+
+struct Events {
+  hipEvent_t a = nullptr, b = nullptr;
+  Events() {
+    DGD_HIP_CHECK(hipEventCreate(&a));
+    DGD_HIP_CHECK(hipEventCreate(&b));
+  }
+  ~Events() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+};
+
+bool valid(const TuneParams& p) {
+  return (p.epw == 1 || p.epw == 2 || p.epw == 4 || p.epw == 8) &&
+         (p.waves == 1 || p.waves == 2 || p.waves == 4) && (p.remap == 0 || p.remap == 1) &&
+         p.grid_per_cu >= 0 && p.grid_per_cu <= 64;
+}
+
+}  // namespace
+
+std::string tune_key(int np, int prec, bool mfma, int R, int64_t E) {
+  const int e2 = E > 0 ? (int)std::floor(std::log2((double)E)) : 0;
+  std::ostringstream k;
+  k << device_info().arch << "|np" << np << "|" << (prec == DGD_FP64 ? "fp64" : "fp32") << "|"
+    << (mfma ? "mfma" : "valu") << "|R" << R << "|E2^" << e2;
+  return k.str();
+}
+
+bool tune_find(const std::string& key, TuneParams* out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_table.find(key);
+  if (it == g_table.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+Shape tune_shape(const TuneParams& p, int64_t E) {
+  const int64_t grid = p.grid_per_cu > 0 ? (int64_t)p.grid_per_cu * device_info().cus : 0;
+  return element_shape(E, p.epw, p.waves, p.remap != 0, grid);
+}
+
+TuneParams tune_stage(const RunTarget& t, int R, bool mfma, void* a, void* b, const void* base,
+                      hipStream_t st) {
+  const int64_t n = t.E * t.np * (int64_t)R;
+  if (t.prec == DGD_FP64)
+    launch_fill_random((double*)a, n, 0x5eedull, st);
+  else
+    launch_fill_random_f32((float*)a, n, 0x5eedull, st);
+  DGD_HIP_CHECK(hipGetLastError());
+  if (!base) base = a;
+  // The timed launch is the common stage (stages 2 and 3 of SSP-RK3): read
+  // the stage input and the base state, write the output,
+  //   out = base + 1/4 (u - base) + g L(u),
+  // with a small g, so the values stay bounded however many launches
+  // alternate between the two buffers.
+  const double g = 1e-3, cb = 0.25;
+  int flip = 0;
+  auto launch = [&](const Shape& sh) {
+    const void* src = flip ? b : a;
+    void* dst = flip ? a : b;
+    flip ^= 1;
+    if (mfma)
+      launch_stage_p3_mfma(src, base, dst, t.elem, t.E, t.Atab, t.Ctab, t.Wtab, t.wsum, 1, cb, g, R,
+                           sh, st);
+    else
+      launch_stage(t.prec == DGD_FP64 ? 0 : 1, t.np, src, base, dst, t.elem, t.E, t.S, t.N, 1, cb,
+                   g, R, sh, st);
+  };
+  Events ev;
+  auto time_ms = [&](const TuneParams& p, int reps) {
+    const Shape sh = tune_shape(p, t.E);
+    launch(sh);
+    launch(sh);
+    DGD_HIP_CHECK(hipEventRecord(ev.a, st));
+    for (int i = 0; i < reps; ++i) launch(sh);
+    DGD_HIP_CHECK(hipEventRecord(ev.b, st));
+    DGD_HIP_CHECK(hipEventSynchronize(ev.b));
+    DGD_HIP_CHECK(hipGetLastError());
+    float ms = 0;
+    DGD_HIP_CHECK(hipEventElapsedTime(&ms, ev.a, ev.b));
+    return (double)ms / reps;
+  };
+
+  std::vector<TuneParams> cand;
+  const int epws_valu[] = {1, 2, 4};
+  for (int epw : epws_valu) {
+    if (mfma && epw != 1) continue;  // the matrix-core kernel takes one element per wave
+    for (int waves : {1, 2, 4})
+      for (int remap : {0, 1})
+        for (int gpc : {0, 4, 8, 16}) {
+          TuneParams p;
+          p.epw = epw;
+          p.waves = waves;
+          p.remap = remap;
+          p.grid_per_cu = gpc;
+          cand.push_back(p);
+        }
+  }
+  // Warm the device up (clocks ramp up under load: a cold start would
+  // favour whatever is timed last) for about 30 ms, then time every
+  // candidate for about 2 ms twice, in forward and in reverse order, keep
+  // the better time, and time the best four again with three times the
+  // launches.
+  double est = time_ms(TuneParams(), 3);
+  for (double spent = 0; spent < 30.0;) {
+    const int n = std::max(3, std::min(200, (int)std::ceil(10.0 / std::max(est, 1e-3))));
+    est = time_ms(TuneParams(), n);
+    spent += std::max(est, 1e-3) * (n + 2);
+  }
+  const int reps = std::max(3, std::min(200, (int)std::ceil(2.0 / std::max(est, 1e-3))));
+  for (auto& p : cand) p.ms = time_ms(p, reps);
+  for (auto it = cand.rbegin(); it != cand.rend(); ++it) it->ms = std::min(it->ms, time_ms(*it, reps));
+  std::sort(cand.begin(), cand.end(),
+            [](const TuneParams& x, const TuneParams& y) { return x.ms < y.ms; });
+  const size_t top = std::min<size_t>(4, cand.size());
+  for (size_t i = 0; i < top; ++i) cand[i].ms = std::min(cand[i].ms, time_ms(cand[i], 3 * reps));
+  std::sort(cand.begin(), cand.begin() + top,
+            [](const TuneParams& x, const TuneParams& y) { return x.ms < y.ms; });
+  const TuneParams best = cand[0];
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_table[tune_key(t.np, t.prec, mfma, R, t.E)] = best;
+  return best;
+}
+
+std::string tune_export() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::ostringstream o;
+  o.precision(6);
+  for (const auto& kv : g_table)
+    o << kv.first << ' ' << kv.second.epw << ' ' << kv.second.waves << ' ' << kv.second.remap << ' '
+      << kv.second.grid_per_cu << ' ' << kv.second.ms << '\n';
+  return o.str();
+}
+
+int tune_import(const std::string& text) {
+  std::istringstream in(text);
+  std::string line;
+  std::vector<std::pair<std::string, TuneParams>> rows;
+  while (std::getline(in, line)) {
+    if (line.empty() || line[0] == '#') continue;
+    std::istringstream ls(line);
+    std::string key;
+    TuneParams p;
+    if (!(ls >> key >> p.epw >> p.waves >> p.remap >> p.grid_per_cu >> p.ms) || !valid(p))
+      throw Error{DGD_EINVAL, "bad tuning table line: " + line};
+    rows.emplace_back(key, p);
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& r : rows) g_table[r.first] = r.second;
+  return (int)rows.size();
+}
+
+void tune_clear() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_table.clear();
+}
+
+}  // namespace dgd

@@ -1,0 +1,43 @@
+// Launch-shape autotuner of the stage kernels (internal).
+//
+// The stage kernels give the same bits for every launch shape (each
+// element and right-hand side is computed by one lane, in a fixed order),
+// so the shape is a pure performance choice.  The tuner times every shape
+// of a small search space on the device and keeps the fastest per key:
+// device architecture, element size Np, state precision, kernel (VALU or
+// matrix core), number of right-hand sides, and the element count rounded
+// down to a power of two.
+#pragma once
+
+#include <string>
+
+#include "dgd_internal.h"
+#include "launch.h"
+
+namespace dgd {
+
+struct TuneParams {
+  int epw = 1;          // elements per wave
+  int waves = 4;        // waves per workgroup (1, 2 or 4)
+  int remap = 1;        // XCD-banded block order
+  int grid_per_cu = 0;  // > 0: persistent grid of this many workgroups per CU
+  double ms = 0;        // measured time of one stage launch
+};
+
+std::string tune_key(int np, int prec, bool mfma, int R, int64_t E);
+bool tune_find(const std::string& key, TuneParams* out);
+Shape tune_shape(const TuneParams& p, int64_t E);
+
+// Time every candidate shape of one stage launch of `t` over R right-hand
+// sides, using a and b (each E * np * R states) as scratch and reading
+// `base` (E * np * R states, finite, left unchanged; NULL: a is filled and
+// read as the base), store the fastest under its key and return it.
+// Synchronises the stream.
+TuneParams tune_stage(const RunTarget& t, int R, bool mfma, void* a, void* b, const void* base,
+                      hipStream_t st);
+
+std::string tune_export();
+int tune_import(const std::string& text);
+void tune_clear();
+
+}  // namespace dgd

@@ -21,6 +21,12 @@ LIB_PATH = os.path.join(_HERE, "libdgd.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libdgd.so not built at {LIB_PATH}: run python -m paper_1907_06191_amd.build")
+try:
+    # PyTorch first, so that the library binds to the HIP runtime PyTorch
+    # loads (its workspaces and streams are then the library's own).
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = ctypes.CDLL(LIB_PATH)
 
 DGD_OK = 0
@@ -95,6 +101,10 @@ _sig("dgd_eap_solve_expm", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, 
                             ctypes.c_double, _c_dp, _c_dp, ctypes.POINTER(ctypes.c_int64)])
 _sig("dgd_eap_solve", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, ctypes.c_int32, _c_dp,
                        _c_dp, _vp, ctypes.c_size_t, _vp])
+_sig("dgd_autotune", [_vp, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_int32), _c_dp])
+_sig("dgd_tune_export", [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)])
+_sig("dgd_tune_import", [ctypes.c_char_p])
+_sig("dgd_tune_clear", [], None)
 
 
 def _check(rc):
@@ -138,6 +148,31 @@ def dgd_version() -> int:
 
 def dgd_set_option(name: str, value: int) -> None:
     _check(_lib.dgd_set_option(name.encode(), int(value)))
+
+
+def dgd_autotune(op, n_points: int, stream=None):
+    """Tune the stage launch shape of op at n_points right-hand sides.
+    Returns (dict(epw, waves, xcd_remap, grid_per_cu), ms per stage launch)."""
+    shape = (ctypes.c_int32 * 4)()
+    ms = ctypes.c_double()
+    _check(_lib.dgd_autotune(op, int(n_points), _stream_ptr(stream), shape, ctypes.byref(ms)))
+    return dict(epw=shape[0], waves=shape[1], xcd_remap=shape[2], grid_per_cu=shape[3]), ms.value
+
+
+def dgd_tune_export() -> str:
+    n = ctypes.c_size_t()
+    _check(_lib.dgd_tune_export(None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(_lib.dgd_tune_export(buf, n.value, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def dgd_tune_import(text: str) -> None:
+    _check(_lib.dgd_tune_import(text.encode()))
+
+
+def dgd_tune_clear() -> None:
+    _lib.dgd_tune_clear()
 
 
 def dgd_mesh_create(L_um: float, n_cells: int, disks) -> int:

@@ -99,3 +99,28 @@ def test_argument_errors_without_device():
     with pytest.raises(dgd.DGDError) as e:
         dgd.dgd_operator_build(m.handle, 2, -2.0, 10.0, dgd.DGD_FP64, 1e-3)
     assert e.value.code == dgd.DGD_EINVAL
+
+
+def test_tuning_table_text_round_trip():
+    """The autotuner's table imports and exports on the host; a bad line is
+    rejected whole and leaves the table unchanged."""
+    from paper_1907_06191_amd import dgd
+    dgd.dgd_tune_clear()
+    assert dgd.dgd_tune_export() == ""
+    text = ("# comment\n"
+            "gfx950|np6|fp32|valu|R64|E2^17 1 4 0 8 0.159\n"
+            "gfx950|np10|fp32|mfma|R128|E2^15 1 2 1 0 0.21\n")
+    dgd.dgd_tune_import(text)
+    rows = sorted(dgd.dgd_tune_export().strip().split("\n"))
+    assert rows == ["gfx950|np10|fp32|mfma|R128|E2^15 1 2 1 0 0.21",
+                    "gfx950|np6|fp32|valu|R64|E2^17 1 4 0 8 0.159"]
+    for bad in ("k 3 4 0 0 1.0\n", "k 1 3 0 0 1.0\n", "k 1 4 2 0 1.0\n", "k 1 4 0 -1 1.0\n",
+                "k 1 4 0\n", "gfx950|x 1 4 0 0 1.0\nk 1 4\n"):
+        with pytest.raises(dgd.DGDError) as e:
+            dgd.dgd_tune_import(bad)
+        assert e.value.code == dgd.DGD_EINVAL
+    assert sorted(dgd.dgd_tune_export().strip().split("\n")) == rows
+    dgd.dgd_tune_clear()
+    assert dgd.dgd_tune_export() == ""
+    assert dgd._lib.dgd_tune_import(None) == dgd.DGD_EINVAL
+    dgd.dgd_set_option("autotune", 1)

@@ -1,0 +1,75 @@
+"""GPU parity at full size: the 512 x 512, phi = 0.6, P2, 64-start-point
+workload, in the launch configuration the benchmark times, against oracle
+values stored by tests/golden/make_full_golden.py (the oracle's Chebyshev
+exponential on the full mesh, 8 sampled start points, all 20 Delta).
+
+* RK3 (FP32 state): the first two Delta (about 53k steps), 1e-4 on Sigma.
+* Chebyshev exponential (FP64 state): every Delta to 50 ms, 1e-8 on Sigma.
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import moments as omom
+from workloads import config, make_geometry, start_points
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_p2_oracle.json")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def case():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    from paper_1907_06191_amd import dgd
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    c = config(gold["workload"])
+    g = make_geometry(c["L"], c["N"], c["geom_seed"], phi=c["phi"], n_disks=c["n_disks"])
+    pts = start_points(g.disks, g.L, g.N, c["R"], np.random.default_rng(c["point_seed"]))
+    idx = np.asarray(gold["sample_index"])
+    assert g.disks.shape[0] == gold["n_disks"]
+    assert np.array_equal(pts[idx], np.asarray(gold["points"]))
+    mesh = dgd.Mesh(g.L, g.N, g.disks)
+    assert mesh.info()["n_active"] == gold["n_elements"]
+    return dgd, c, gold, mesh, pts, idx
+
+
+def test_fullsize_rk3_fp32_first_deltas(case):
+    dgd, c, gold, mesh, pts, idx = case
+    nd = 2
+    say(f"full-size RK3 P{gold['p']} FP32: {gold['n_elements']} elements, {pts.shape[0]} points, "
+        f"dt {gold['dt_nom']:.4e} ms, Delta {gold['deltas'][:nd]}")
+    op = dgd.Operator(mesh, gold["p"], c["D"], c["eta"], dgd.DGD_FP32, dt_max_ms=gold["dt_nom"])
+    sig, mom = op.solve(pts, c["sigma0"], gold["deltas"][:nd])
+    ref = omom.sigma_a(np.asarray(gold["moments"])[:, :nd])
+    err = omom.rel_err(sig[idx], ref)
+    drift = np.abs(mom[..., 0] - 1).max()
+    say(f"  max rel err vs oracle {err.max():.2e}; |M0-1| {drift:.2e}")
+    assert err.max() < 1e-4
+    assert drift < 1e-5
+    op.close()
+
+
+def test_fullsize_expm_all_deltas(case):
+    dgd, c, gold, mesh, pts, idx = case
+    say(f"full-size Chebyshev exponential P{gold['p']}: {len(gold['deltas'])} Delta to "
+        f"{gold['deltas'][-1]:.0f} ms")
+    op = dgd.Operator(mesh, gold["p"], c["D"], c["eta"], dgd.DGD_FP32, dt_max_ms=gold["dt_nom"])
+    sig, mom, napp = dgd.dgd_eap_solve_expm(op.handle, pts, c["sigma0"], gold["deltas"])
+    ref = omom.sigma_a(np.asarray(gold["moments"]))
+    err = omom.rel_err(sig[idx], ref)
+    say(f"  {napp} operator applications; max rel err vs oracle {err.max():.2e}")
+    assert err.max() < 1e-8
+    op.close()

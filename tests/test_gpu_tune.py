@@ -1,0 +1,72 @@
+"""GPU: the stage-kernel autotuner.  Tuned shapes are valid, land in the
+table under their key, and change no bit of a solve (every launch shape
+computes each element and right-hand side in the same lane order)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from workloads import make_geometry, start_points
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dgd():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    from paper_1907_06191_amd import dgd as d
+    return d
+
+
+def _case(nrhs, N=64, seed=41):
+    h = 100.0 / 512
+    g = make_geometry(N * h, N, 19070619 + 900 + seed, phi=0.6)
+    pts = start_points(g.disks, g.L, g.N, nrhs, np.random.default_rng(19070619 + 901 + seed))
+    return g, pts
+
+
+@pytest.mark.parametrize("p,R,kernel", [(2, 64, "valu"), (1, 16, "valu"), (3, 16, "mfma")])
+def test_autotune_shape_valid_and_bit_invariant(dgd, p, R, kernel):
+    g, pts = _case(R)
+    mesh = dgd.Mesh(g.L, g.N, g.disks)
+    op = dgd.Operator(mesh, p, 2.0, 10.0, dgd.DGD_FP32)   # stable step from the auto rule
+    E = mesh.info()["n_active"]
+    say(f"autotune p={p} R={R} ({kernel}), {E} elements")
+    dgd.dgd_tune_clear()
+    shape, ms = dgd.dgd_autotune(op.handle, R)
+    say(f"  best {shape}, {ms * 1e3:.1f} us per stage launch")
+    assert shape["epw"] in (1, 2, 4) and shape["waves"] in (1, 2, 4)
+    assert shape["xcd_remap"] in (0, 1) and shape["grid_per_cu"] in (0, 4, 8, 16)
+    if kernel == "mfma":
+        assert shape["epw"] == 1
+    assert 0 < ms < 100
+    table = dgd.dgd_tune_export()
+    key = f"|np{(p + 1) * (p + 2) // 2}|fp32|{kernel}|R{R}|E2^{int(np.floor(np.log2(E)))} "
+    assert key in table, table
+    deltas = [0.002, 0.004]
+    sig_t, mom_t = op.solve(pts, 0.3, deltas)
+    dgd.dgd_set_option("autotune", 0)
+    try:
+        for epw, waves, grid in ((1, 4, 0), (2, 1, 512)):
+            if kernel == "mfma" and epw != 1:
+                continue
+            dgd.dgd_set_option("stage_epw", epw)
+            dgd.dgd_set_option("stage_waves", waves)
+            dgd.dgd_set_option("stage_grid", grid)
+            sig_o, mom_o = op.solve(pts, 0.3, deltas)
+            assert np.array_equal(mom_t, mom_o), (epw, waves, grid)
+    finally:
+        dgd.dgd_set_option("autotune", 1)
+        dgd.dgd_set_option("stage_epw", 1)
+        dgd.dgd_set_option("stage_waves", 4)
+        dgd.dgd_set_option("stage_grid", 0)
+    op.close()
+    mesh.close()
