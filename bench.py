@@ -40,6 +40,22 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes (FETCH_SIZE calibrated x 2.000, WRITE_SIZE x 1.000 by a
+# plain 1 GiB copy), keyed by (workload, kernel, sha256 prefix of
+# csrc/kernels.hip when the counters were taken).  A kernel source that
+# has changed since reports traffic null.  Summaries: profiles/.
+MEASURED_TRAFFIC = {
+    ("C2", "k_stage<float,6>", "49fd7d0af5878cac"): 1166.7e6,
+}
+
+
+def kernel_source_tag():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1907_06191_amd", "csrc", "kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -153,10 +169,13 @@ def plain(args):
     out["sigma_solves_note"] = ("RK3 path, projected: measured ms/step x the full Delta-landing "
                                 "schedule + measured moment reduction per Delta")
     out["mass_after_timed"] = float(np.abs(mom[:, 0] - 1).max())
+    traffic = MEASURED_TRAFFIC.get((args.workload, kernel, kernel_source_tag()))
     out["roofline"] = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
-        "bytes_per_launch": bytes_per_launch, "launch_ms": round(launch_ms, 5)}
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+        "bytes_per_launch": bytes_per_launch, "launch_ms": round(launch_ms, 5),
+        "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated), "
+                        "null unless measured on this kernel source"}
     run.close()
     if args.expm:
         torch.cuda.synchronize()
