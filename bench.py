@@ -18,8 +18,8 @@ Also reported:
   * Sigma-solves/s measured end to end (initial projection, the whole
     Delta list, moments) with the Chebyshev exponential integrator
     (--no-expm skips it);
-  * --workload C3: the batched solve (256 uneven geometries, P1/P2 groups,
-    16 start points each); --workload C4: P3 on matrix cores, 128 start
+  * --workload batch256-p12: the batched solve (256 uneven geometries, P1/P2
+    groups, 16 start points each); --workload pack256-p3: P3 on matrix cores, 128 start
     points.
 
 Prints one JSON line.
@@ -46,7 +46,7 @@ HBM_PEAK_GBS = 8000.0
 # csrc/kernels.hip when the counters were taken).  A kernel source that
 # has changed since reports traffic null.  Summaries: profiles/.
 MEASURED_TRAFFIC = {
-    ("C2", "k_stage<float,6>", "49fd7d0af5878cac"): 1166.7e6,
+    ("pack512-p2", "k_stage<float,6>", "49fd7d0af5878cac"): 1166.7e6,
 }
 
 
@@ -206,12 +206,12 @@ def plain(args):
 def batched(args):
     import torch
     from paper_1907_06191_amd import dgd
-    from workloads import c3_workload, config
+    from workloads import batch_workload, config
 
-    c = config("C3")
+    c = config("batch256-p12")
     n = args.geoms or c["n_geoms"]
     t0 = time.time()
-    work = c3_workload(n, workers=args.workers)
+    work = batch_workload(n, workers=args.workers)
     log(f"{n} geometries in {time.time() - t0:.0f}s")
     meshes = [dgd.Mesh(g.L, g.N, g.disks) for g, _, _ in work]
     ops = [dgd.Operator(m, p, c["D"], c["eta"], dgd.DGD_FP32) for m, (_, _, p) in zip(meshes, work)]
@@ -236,7 +236,7 @@ def batched(args):
     mom = b.moments(check=False)
     value = total_updates / (total_ms * 1e-3) / 1e9
     out = base_record(args, value, total_ms / args.steps, "f64 arithmetic, f32 state", {
-        "workload": f"C3: batched solve, {n} geometries (grid edge 128..512 at h=100/512 um, "
+        "workload": f"batch256-p12: batched solve, {n} geometries (grid edge 128..512 at h=100/512 um, "
                     f"phi 0.4..0.7), P1/P2 groups, {R} start points each",
         "groups": per_group})
     out["stage_shape_table"] = dgd.dgd_tune_export().strip().split("\n")
@@ -252,9 +252,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4"])
+    ap.add_argument("--workload", default="pack512-p2",
+                    choices=["box20-p1", "pack512-p2", "batch256-p12", "pack256-p3"])
     ap.add_argument("--p", type=int, default=None, help="override polynomial degree")
-    ap.add_argument("--geoms", type=int, default=0, help="C3: number of geometries (default all)")
+    ap.add_argument("--geoms", type=int, default=0, help="batch256-p12: number of geometries (default all)")
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-expm", dest="expm", action="store_false")
@@ -275,7 +276,7 @@ def main():
     if args.tune_file and os.path.exists(args.tune_file):
         with open(args.tune_file) as f:
             dgd.dgd_tune_import(f.read())
-    out = batched(args) if args.workload == "C3" else plain(args)
+    out = batched(args) if args.workload == "batch256-p12" else plain(args)
     if args.tune_file:
         with open(args.tune_file, "w") as f:
             f.write(dgd.dgd_tune_export())

@@ -49,7 +49,7 @@ extern "C" {
 /* Precision of operator and state.  Moments are always reduced in FP64. */
 #define DGD_FP64 0
 #define DGD_FP32 1
-#define DGD_BF16X3 2        /* P3 only: BF16 hi/lo split products on MFMA, FP32 accumulate/state */
+#define DGD_BF16X3 2        /* reserved (BF16 hi/lo split products): rejected with EINVAL */
 
 typedef struct dgd_mesh dgd_mesh;
 typedef struct dgd_op dgd_op;
@@ -96,7 +96,8 @@ void dgd_mesh_destroy(dgd_mesh* mesh);
  * Build the SIPG operator of degree p on the mesh (section 3.1 with the
  * interior-penalty flux; section 3.2 for the role of the flux).
  *   p in {1, 2, 3}; D > 0 (um^2/ms); eta > 0 (penalty eta p^2 D / h);
- *   precision: DGD_FP64, DGD_FP32, or DGD_BF16X3 (p = 3 only);
+ *   precision: DGD_FP64 or DGD_FP32 (state precision; with DGD_FP32, P3
+ *     stages run on matrix cores when the right-hand-side count allows);
  *   dt_max_ms > 0: nominal step = min(0.1 h^2 / (D (p+1)^2), dt_max_ms);
  *   dt_max_ms <= 0: nominal step = min(0.1 h^2 / (D (p+1)^2), 0.9 X / b),
  *     X = 2.5127... the real stability limit of SSP-RK3 and

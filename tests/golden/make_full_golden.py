@@ -1,6 +1,6 @@
 """Write oracle values for parity at a workload's full size.
 
-    python tests/golden/make_full_golden.py C2 --sample 8 --workers 8
+    python tests/golden/make_full_golden.py pack512-p2 --sample 8 --workers 8
 
 Builds the workload's seeded geometry and start points, assembles the FP64
 oracle on the full mesh, and carries a sample of the start points (every
@@ -57,8 +57,9 @@ def main():
         sample_index=[int(i) for i in idx], points=pts[idx].tolist(), deltas=list(c["deltas"]),
         moments=mom.tolist(), oracle_seconds=el, oracle_workers=args.workers,
     )
+    name = args.workload if args.p is None else f"{args.workload}_p{p}"
     path = args.out or os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                    f"{args.workload.lower()}_p{p}_oracle.json")
+                                    f"{name}_oracle.json")
     with open(path, "w") as f:
         json.dump(out, f)
     print("wrote", path, flush=True)

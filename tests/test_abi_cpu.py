@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
-@pytest.mark.parametrize("name", ["C1", "C4"])
+@pytest.mark.parametrize("name", ["box20-p1", "pack256-p3"])
 @pytest.mark.parametrize("strip", [0, 64, 24])
 def test_host_mesh_matches_oracle_mesh(name, strip):
     from paper_1907_06191_amd import dgd

@@ -19,7 +19,8 @@ from workloads import config, make_geometry, start_points
 
 pytestmark = pytest.mark.gpu
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_p2_oracle.json")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "pack512-p2_oracle.json")
 
 
 def say(msg):

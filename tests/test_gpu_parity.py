@@ -87,7 +87,7 @@ def test_V10_operator_extraction(dgd, p, prec):
 
 
 def _c1_setup():
-    c = config("C1")
+    c = config("box20-p1")
     g = make_geometry(c["L"], c["N"], c["geom_seed"], n_disks=c["n_disks"])
     pts = start_points(g.disks, g.L, g.N, 1, np.random.default_rng(c["point_seed"]))
     return c, g, pts
@@ -99,7 +99,7 @@ def test_c1_parity_fp64(dgd):
     c, g, pts = _c1_setup()
     prob = osolve.prepare(g.L, g.N, g.disks, c["p"], c["D"], c["eta"])
     dt = prob.dt["dt_nom"]
-    say(f"C1 parity FP64: {prob.op.mesh.n_elements} elements, dt={dt:.4e} ms")
+    say(f"box20-p1 parity FP64: {prob.op.mesh.n_elements} elements, dt={dt:.4e} ms")
     ref = osolve.solve(prob, pts, c["sigma0"], c["deltas"], method="rk3")
     mesh = dgd.Mesh(g.L, g.N, g.disks)
     op = dgd.Operator(mesh, c["p"], c["D"], c["eta"], dgd.DGD_FP64, dt_max_ms=dt)
@@ -113,7 +113,7 @@ def test_c1_parity_fp64(dgd):
 
 
 def _small_dense_case(nrhs=8, N=64, seed=7):
-    """A 12.5 um box at the C2 grid spacing (h = 100/512) and packing 0.6."""
+    """A 12.5 um box at the 512-grid spacing (h = 100/512) and packing 0.6."""
     h = 100.0 / 512
     L = N * h
     g = make_geometry(L, N, 19070619 + 900 + seed, phi=0.6)
@@ -123,7 +123,7 @@ def _small_dense_case(nrhs=8, N=64, seed=7):
 
 @pytest.mark.parametrize("p", [1, 2])
 def test_fp32_parity_dense_packing(dgd, p):
-    """FP32 state and operator, FP64 moments, on a dense packing at the C2
+    """FP32 state and operator, FP64 moments, on a dense packing at the 512-grid
     grid spacing: Sigma within 1e-4 of the oracle's exact flow (Chebyshev)
     at Delta = 0.5 and 1 ms (about 22k and 44k RK3 steps for P2)."""
     g, pts = _small_dense_case()

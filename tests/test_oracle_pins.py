@@ -363,7 +363,7 @@ def test_V13_chebyshev_matches_rk3_on_small_workload():
     small workload's mesh (RK3 time error is negligible for the modes that
     carry Sigma)."""
     from workloads import config, make_geometry, start_points
-    c = config("C1")
+    c = config("box20-p1")
     g = make_geometry(c["L"], c["N"], c["geom_seed"], n_disks=c["n_disks"])
     pts = start_points(g.disks, g.L, g.N, 1, np.random.default_rng(c["point_seed"]))
     prob = osolve.prepare(g.L, g.N, g.disks, c["p"], c["D"], c["eta"])

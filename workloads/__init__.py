@@ -10,4 +10,4 @@ the other through it.
 """
 
 from .geometry import rsa_disks, start_points, Geometry, make_geometry  # noqa: F401
-from .configs import CONFIGS, config, c3_geometry_params, c3_workload  # noqa: F401
+from .configs import CONFIGS, config, batch_geometry_params, batch_workload  # noqa: F401
