@@ -90,6 +90,12 @@ int dgd_mesh_info(const dgd_mesh* mesh, int64_t* n_active, int64_t* n_faces,
  * n_active; any may be NULL. */
 int dgd_mesh_elements(const dgd_mesh* mesh, int32_t* cell_i, int32_t* cell_j, int8_t* orient);
 
+/* Face neighbours on the host: for every active triangle in solver order,
+ * the element across its faces 0, 1, 2 (T0: bottom, right, diagonal; T1:
+ * top, left, diagonal; section 3.3 pixel split), -1 where the face carries
+ * no flux.  nbr_out: int32 [n_active][3]. */
+int dgd_mesh_faces(const dgd_mesh* mesh, int32_t* nbr_out);
+
 void dgd_mesh_destroy(dgd_mesh* mesh);
 
 /*
@@ -295,6 +301,12 @@ void dgd_surrogate_destroy(dgd_surrogate* s);
  *                  right-hand-side count is a multiple of 16
  *   "mesh_strip"   element order of meshes created afterwards: vertical strips
  *                  of this many cell columns, each row-major (0 = plain rows)
+ *   "mesh_group"   element order of meshes created afterwards: the ranked
+ *                  cells in runs of this many, each run giving the T0
+ *                  triangles of its cells, then their T1 (default 4; 1 = T0,
+ *                  T1 per cell), so that aligned runs share an orientation
+ *   "packed"       1 (default) = runs with at most 32 right-hand sides use the
+ *                  packed stage kernel (4 or 2 elements per wave)
  *   "autotune"     1 (default) = runs take the tuned stage launch shape of
  *                  their key, tuning it when the run is created if the key
  *                  is new; 0 = the shape options above

@@ -39,6 +39,8 @@ struct Options {
   bool xcd_remap = true;    // XCD-banded block order
   int64_t stage_grid = 0;   // > 0: persistent stage kernel with this many workgroups
   int mesh_strip = 64;      // element order: vertical strips of this many cell columns (0: rows)
+  int mesh_group = 4;       // element order: runs of this many cells give their T0, then their T1
+  bool packed = true;       // R <= 32: several elements per wave (packed stage kernel)
   bool p3_mfma = true;      // P3 FP32 stages on matrix cores when R % 16 == 0
   bool autotune = true;     // tune the stage launch shape per key on first use
 };
@@ -119,6 +121,7 @@ RunTarget plain_target(const dgd_op* op) {
   t.prec = op->precision;
   t.S = op->d_S;
   t.N = op->d_N;
+  t.F = op->d_F;
   t.D = op->D;
   t.h = op->mesh->host.h;
   t.W = op->d_W;
@@ -140,27 +143,71 @@ bool use_p3_mfma(const RunTarget& t, int R) {
          (double)t.E * 10.0 * (double)R < 2147483647.0;
 }
 
-// Launch shape of the stage kernel on (t, R): the tuned one for its key
-// when autotuning is on and the key has been tuned, else the options.
-Shape pick_shape(const RunTarget& t, int R) {
-  const bool mfma = use_p3_mfma(t, R);
+// The stage kernel a run of (t, R) uses: matrix cores for P3 FP32 when R
+// is a multiple of 16; for R <= 32 the packed kernel (several elements per
+// wave); else one element and up to 64 right-hand sides per wave.
+enum StageKind { kValu = 0, kPacked = 1, kMfma = 2 };
+const char* const kKindName[3] = {"valu", "packed", "mfma"};
+
+StageKind stage_kind(const RunTarget& t, int R) {
+  if (use_p3_mfma(t, R)) return kMfma;
+  if (g_opt.packed && t.F && R <= 32) return kPacked;
+  return kValu;
+}
+
+int packed_group(int R) { return R <= 16 ? 4 : 2; }
+
+// Work units a stage launch shape counts: elements, or element groups of
+// the packed kernel.
+int64_t stage_units(const RunTarget& t, int R, StageKind k) {
+  if (k != kPacked) return t.E;
+  const int G = packed_group(R);
+  return (t.E + G - 1) / G;
+}
+
+// Launch shape of the stage kernel of `kind` on (t, R): the tuned one for
+// its key when autotuning is on and the key has been tuned, else the
+// options.
+Shape pick_shape(const RunTarget& t, int R, StageKind kind) {
+  const int64_t units = stage_units(t, R, kind);
   if (g_opt.autotune) {
     TuneParams p;
-    if (tune_find(tune_key(t.np, t.prec, mfma, R, t.E), &p)) return tune_shape(p, t.E);
+    if (tune_find(tune_key(t.np, t.prec, kKindName[kind], R, t.E), &p)) return tune_shape(p, units);
   }
-  return element_shape(t.E, mfma ? 1 : g_opt.stage_epw, g_opt.stage_waves, g_opt.xcd_remap,
-                       g_opt.stage_grid);
+  return element_shape(units, kind == kMfma ? 1 : g_opt.stage_epw, g_opt.stage_waves,
+                       g_opt.xcd_remap, g_opt.stage_grid);
 }
+Shape pick_shape(const RunTarget& t, int R) { return pick_shape(t, R, stage_kind(t, R)); }
 
 void stage(const RunTarget& t, const Shape& sh, const void* us, const void* ub, void* out, int mode,
            double cb, double cg, int R, hipStream_t st) {
-  if (use_p3_mfma(t, R)) {
-    launch_stage_p3_mfma(us, ub, out, t.elem, t.E, t.Atab, t.Ctab, t.Wtab, t.wsum, mode, cb, cg, R,
-                         sh, st);
-  } else {
-    launch_stage(t.prec == DGD_FP64 ? 0 : 1, t.np, us, ub, out, t.elem, t.E, t.S, t.N, mode, cb, cg,
-                 R, sh, st);
+  switch (stage_kind(t, R)) {
+    case kMfma:
+      launch_stage_p3_mfma(us, ub, out, t.elem, t.E, t.Atab, t.Ctab, t.Wtab, t.wsum, mode, cb, cg,
+                           R, sh, st);
+      break;
+    case kPacked:
+      launch_stage_packed(t.prec == DGD_FP64 ? 0 : 1, t.np, packed_group(R), us, ub, out, t.elem,
+                          t.E, t.S, t.F, t.N, mode, cb, cg, R, sh, st);
+      break;
+    default:
+      launch_stage(t.prec == DGD_FP64 ? 0 : 1, t.np, us, ub, out, t.elem, t.E, t.S, t.N, mode, cb,
+                   cg, R, sh, st);
   }
+}
+
+// Tune the stage launch shape of (t, R) with a and b as scratch (and base
+// read, NULL: a): the common stage out = base + 1/4 (u - base) + g L(u)
+// with a small g, so the values stay bounded over the timed launches.
+TuneParams tune_target(const RunTarget& t, int R, void* a, void* b, const void* base,
+                       hipStream_t st) {
+  const StageKind kind = stage_kind(t, R);
+  const std::string key = tune_key(t.np, t.prec, kKindName[kind], R, t.E);
+  auto one = [&](const Shape& sh, const void* src, const void* bs, void* dst) {
+    stage(t, sh, src, bs, dst, 1, 0.25, 1e-3, R, st);
+  };
+  return tune_stage(key, stage_units(t, R, kind), t.prec, t.E * t.np * (int64_t)R, kind == kMfma,
+                    a, b, base, one, st);
 }
 
 // Tables of the P3 matrix-core kernel: for class (o, mask) the stacked
@@ -341,8 +388,8 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
     // buffers are free until the first step)
     if (g_opt.autotune) {
       TuneParams p;
-      if (!tune_find(tune_key(t.np, t.prec, use_p3_mfma(t, R), R, t.E), &p))
-        tune_stage(t, R, use_p3_mfma(t, R), run->U1, run->U2, run->U, run->stream);
+      if (!tune_find(tune_key(t.np, t.prec, kKindName[stage_kind(t, R)], R, t.E), &p))
+        tune_target(t, R, run->U1, run->U2, run->U, run->stream);
     }
     run->sh = pick_shape(t, R);
     const Shape shr = reduce_shape(t.E);
@@ -584,6 +631,11 @@ int dgd_set_option(const char* name, int64_t value) {
     } else if (n == "mesh_strip") {
       if (value < 0 || value > 16384) fail(DGD_EINVAL, "mesh_strip must be in [0, 16384]");
       g_opt.mesh_strip = (int)value;
+    } else if (n == "mesh_group") {
+      if (value < 1 || value > 64) fail(DGD_EINVAL, "mesh_group must be in [1, 64]");
+      g_opt.mesh_group = (int)value;
+    } else if (n == "packed") {
+      g_opt.packed = value != 0;
     } else if (n == "autotune") {
       g_opt.autotune = value != 0;
     } else fail(DGD_EINVAL, "unknown option " + n);
@@ -609,8 +661,7 @@ int dgd_autotune(dgd_op* op, int32_t n_points, void* hip_stream, int32_t* shape_
       launch_fill_random((double*)c, n, 0xba5eull, (hipStream_t)hip_stream);
     else
       launch_fill_random_f32((float*)c, n, 0xba5eull, (hipStream_t)hip_stream);
-    const TuneParams p = tune_stage(t, n_points, use_p3_mfma(t, n_points), a, b, c,
-                                    (hipStream_t)hip_stream);
+    const TuneParams p = tune_target(t, n_points, a, b, c, (hipStream_t)hip_stream);
     if (shape_out) {
       shape_out[0] = p.epw;
       shape_out[1] = p.waves;
@@ -660,7 +711,7 @@ int dgd_mesh_create(double L_um, int32_t n_cells, const double* disks, int32_t n
         if (!std::isfinite(disks[3 * d + k])) fail(DGD_EINVAL, "disk list holds a non-finite value");
     auto* m = new dgd_mesh();
     try {
-      build_mesh_host(L_um, n_cells, disks, n_disks, g_opt.mesh_strip, m->host);
+      build_mesh_host(L_um, n_cells, disks, n_disks, g_opt.mesh_strip, g_opt.mesh_group, m->host);
       const int64_t E = m->host.n_elements();
       if (E > ((int64_t)1 << 31) - 1) fail(DGD_EINVAL, "too many elements");
       std::vector<int4> pk(E);
@@ -711,6 +762,14 @@ int dgd_mesh_elements(const dgd_mesh* mesh, int32_t* cell_i, int32_t* cell_j, in
   });
 }
 
+int dgd_mesh_faces(const dgd_mesh* mesh, int32_t* nbr_out) {
+  return guarded([&]() -> int {
+    if (!mesh || !nbr_out) fail(DGD_EINVAL, "NULL argument");
+    std::memcpy(nbr_out, mesh->host.nbr.data(), mesh->host.nbr.size() * sizeof(int32_t));
+    return DGD_OK;
+  });
+}
+
 int dgd_mesh_occupancy(const dgd_mesh* mesh, int32_t size, uint8_t* image_out) {
   return guarded([&]() -> int {
     if (!mesh || !image_out || size < 1 || size > 16384) fail(DGD_EINVAL, "bad argument");
@@ -756,6 +815,7 @@ int dgd_operator_build(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, dou
       // element matrices stay FP64 for both state precisions (FP64 element arithmetic)
       op->d_S = upload(R.S);
       op->d_N = upload(R.Nb);
+      op->d_F = upload(R.Fs);
       op->d_Minv = (double*)upload(R.Minv);
       const double h = mesh->host.h;
       std::vector<double> Wp(R.W.size()), Mp(R.Mass.size());
@@ -836,6 +896,7 @@ void dgd_operator_destroy(dgd_op* op) {
   if (!op) return;
   (void)hipFree(op->d_S);
   (void)hipFree(op->d_N);
+  (void)hipFree(op->d_F);
   (void)hipFree(op->d_Minv);
   (void)hipFree(op->d_W);
   (void)hipFree(op->d_Mass);
@@ -967,7 +1028,8 @@ int dgd_eap_solve_expm(dgd_op* op, const double* points, int32_t n_points, doubl
     DGD_HIP_CHECK(hipMalloc(&buf, (size_t)n * sizeof(double)));
     double* res = (double*)run->U;   // u, then the running sum
     double* T[3] = {(double*)run->U1, (double*)run->U2, buf};
-    const Shape sh = run->sh;
+    // the recurrence runs the one-element-per-wave kernel
+    const Shape sh = pick_shape(t, n_points, kValu);
     const double cg = 2.0 * t.D / (b * t.h * t.h);    // X = I + (2 / b) L, L = (D / h^2) Lhat
     int64_t applies = 0;
     std::vector<double> mom((size_t)n_points * 6);

@@ -50,6 +50,8 @@ struct RefElem {
   std::vector<double> nodes;        // [2][np][2] cell-local positions (units of h)
   std::vector<double> S;            // [2][8][np][np]  -M^-1 (K + sum_{f in mask} Fself_f)
   std::vector<double> Nb;           // [2][3][np][np]  -M^-1 Fnbr_f
+  std::vector<double> Fs;           // [2][3][np][np]  -M^-1 Fself_f: S_{o,7} - S_{o,mask} =
+                                    //   sum over faces f not in mask of Fs_{o,f}
   std::vector<double> Mass;         // [2][np][np]
   std::vector<double> Minv;         // [2][np][np]
   std::vector<double> W;            // [2][6][np] int phi_j xi^a eta^b over the triangle,
@@ -58,7 +60,11 @@ struct RefElem {
 
 RefElem build_ref_elem(int p, double eta);
 std::vector<double> build_ic_quadrature(const RefElem& R, int n);
-void build_mesh_host(double L, int N, const double* disks, int n_disks, int strip, MeshHost& m);
+// Element order: cells ranked in vertical strips of `strip` columns (each
+// strip row by row; strip <= 0: plain rows); the ranked cells are taken in
+// runs of `group` cells, each run giving the T0 of its cells, then their T1.
+void build_mesh_host(double L, int N, const double* disks, int n_disks, int strip, int group,
+                     MeshHost& m);
 
 }  // namespace dgd
 
@@ -78,6 +84,7 @@ struct dgd_op {
   double dt_nom = 0, lambda_max = 0;
   void* d_S = nullptr;    // [2][8][np][np] FP64
   void* d_N = nullptr;    // [2][3][np][np] FP64
+  void* d_F = nullptr;    // [2][3][np][np] FP64 self-face blocks (packed stage kernel)
   double* d_Minv = nullptr;  // [2][np][np] FP64
   double* d_W = nullptr;     // [2][6][np] FP64 physical moment weights
   double* d_Mass = nullptr;  // [2][np][np] FP64 physical mass
@@ -101,6 +108,7 @@ struct RunTarget {
   int np = 0, prec = 0;
   const void* S = nullptr;       // FP64 [2][8][np][np]
   const void* N = nullptr;       // FP64 [2][3][np][np]
+  const void* F = nullptr;       // FP64 [2][3][np][np] self-face blocks
   double D = 0, h = 0;
   const double* W = nullptr;     // physical moment weights [2][6][np]
   const double* Minv = nullptr;  // reference inverse mass [2][np][np]

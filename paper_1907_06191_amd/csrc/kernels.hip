@@ -309,6 +309,144 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
   }
 }
 
+// Packed stage for few right-hand sides (R <= 64 / G): each wave carries G
+// elements side by side, lane l on element (group base + l / (64 / G)) and
+// right-hand side l % (64 / G), so no lane idles when R = 16 (G = 4) or
+// R = 32 (G = 2).  Face masks then differ across the wave, so the operator
+// is used in the split form
+//   S_{o,mask} = S_{o,7} - sum_{f not in mask} F_{o,f},
+// F_{o,f} = -M^-1 (self-face block of face f): every matrix stays
+// wave-uniform (SGPR operands) given the orientation.  Per face, a lane
+// accumulates N_{o,f}(u_f - c) if it has the face and -F_{o,f}(u - c) if
+// not, by zeroing the other product's vector: a product with an exact zero
+// vector leaves the accumulator unchanged (it never holds -0), so a lane
+// computes the same bits whatever the masks of the other elements of its
+// wave, and with all faces present (the common case) the F products are
+// skipped outright.  Waves whose elements mix the
+// two orientations (rare: meshes are ordered in orientation groups of four)
+// run once per orientation under a lane mask.  Modes and combine as in
+// k_stage (0 apply, 1 SSP-RK3 stage).
+template <typename TS, int NP, int G>
+__global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us, const TS* ub,
+                                                      TS* out, const int4* __restrict__ elem,
+                                                      int64_t E, const double* __restrict__ S,
+                                                      const double* __restrict__ Fm,
+                                                      const double* __restrict__ Nm, int mode,
+                                                      double cb, double cg, int R, int epw,
+                                                      int64_t nblocks, int remap) {
+  constexpr int RL = WAVE / G;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int g = lane / RL;
+  const int r_raw = lane % RL;
+  const bool live_r = r_raw < R;
+  const int r = live_r ? r_raw : R - 1;
+  const bool use_base = ub != nullptr;
+  const BlockIter it = block_iter(nblocks, remap);
+  for (int64_t b = it.first; b < it.end; b += it.stride) {
+    const int64_t q0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
+    for (int k = 0; k < epw; ++k) {
+      const int64_t eg = (q0 + k) * G;          // first element of the group
+      if (eg >= E) break;
+      const int64_t e_raw = eg + g;
+      const bool live = live_r && e_raw < E;
+      const int64_t e = e_raw < E ? e_raw : E - 1;
+      const int4 m = elem[e];
+      const int o = m.w & 1;
+      const int mask = (m.w >> 1) & 7;
+      // wave-uniform facts: orientation of lane 0, whether any lane differs,
+      // whether any element misses a face
+      const int o0 = __builtin_amdgcn_readfirstlane(o);
+      const bool mixed = __ballot(o != o0) != 0;
+      const bool partial = __ballot(mask != 7) != 0;
+      // one element and right-hand side per lane with orientation oo (uniform)
+      auto body = [&](const int oo) {
+        const int64_t self = (e * NP) * (int64_t)R + r;
+        const int64_t n0 = (m.x >= 0 ? (int64_t)m.x * NP * R + r : self);
+        const int64_t n1 = (m.y >= 0 ? (int64_t)m.y * NP * R + r : self);
+        const int64_t n2 = (m.z >= 0 ? (int64_t)m.z * NP * R + r : self);
+        TS su[NP], s0[NP], s1[NP], s2[NP], sb[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+          su[j] = us[self + (int64_t)j * R];
+          s0[j] = us[n0 + (int64_t)j * R];
+          s1[j] = us[n1 + (int64_t)j * R];
+          s2[j] = us[n2 + (int64_t)j * R];
+        }
+        if (use_base) {
+#pragma unroll
+          for (int j = 0; j < NP; ++j) sb[j] = ub[self + (int64_t)j * R];
+        }
+        const double c = (double)su[0];
+        double d[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) d[j] = (double)su[j] - c;
+        double acc[NP];
+        {
+          const double* Se = S + (oo * 8 + 7) * NP * NP;
+#pragma unroll
+          for (int i = 0; i < NP; ++i) {
+            double a = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) a = fma(Se[i * NP + j], d[j], a);
+            acc[i] = a;
+          }
+        }
+#define DGD_PFACE(F, SV)                                                                     \
+        {                                                                                    \
+          const double* Nf = Nm + (oo * 3 + F) * NP * NP;                                    \
+          const bool has = !partial || ((mask >> F) & 1);                                    \
+          double dn[NP];                                                                     \
+          _Pragma("unroll") for (int j = 0; j < NP; ++j) dn[j] = has ? (double)SV[j] - c : 0.0; \
+          _Pragma("unroll") for (int i = 0; i < NP; ++i) {                                   \
+            double a = acc[i];                                                               \
+            _Pragma("unroll") for (int j = 0; j < NP; ++j) a = fma(Nf[i * NP + j], dn[j], a); \
+            acc[i] = a;                                                                      \
+          }                                                                                  \
+          if (partial) {                                                                     \
+            const double* Ff = Fm + (oo * 3 + F) * NP * NP;                                  \
+            double dm[NP];                                                                   \
+            _Pragma("unroll") for (int j = 0; j < NP; ++j) dm[j] = has ? 0.0 : d[j];         \
+            _Pragma("unroll") for (int i = 0; i < NP; ++i) {                                 \
+              double a = acc[i];                                                             \
+              _Pragma("unroll") for (int j = 0; j < NP; ++j) a = fma(-Ff[i * NP + j], dm[j], a); \
+              acc[i] = a;                                                                    \
+            }                                                                                \
+          }                                                                                  \
+        }
+        DGD_PFACE(0, s0)
+        DGD_PFACE(1, s1)
+        DGD_PFACE(2, s2)
+#undef DGD_PFACE
+        if (!live) return;
+        if (mode == 0) {
+#pragma unroll
+          for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)(cg * acc[i]);
+        } else if (use_base) {
+#pragma unroll
+          for (int i = 0; i < NP; ++i) {
+            const double b0 = (double)sb[i];
+            store_state(out, self + (int64_t)i * R, b0 + cb * ((double)su[i] - b0) + cg * acc[i],
+                        state_salt(m.w, i * R + r));
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < NP; ++i)
+            store_state(out, self + (int64_t)i * R, (double)su[i] + cg * acc[i],
+                        state_salt(m.w, i * R + r));
+        }
+      };
+      if (!mixed) {
+        body(o0);
+      } else if (o == 0) {
+        body(0);
+      } else {
+        body(1);
+      }
+    }
+  }
+}
+
 // Reduction kernels share one shape: 4 waves per workgroup, each wave walks
 // `epw` consecutive elements, lanes on right-hand sides; per-block partials
 // part[b][r][6] are summed later in a fixed order (deterministic).
@@ -638,6 +776,27 @@ void launch_stage(int prec, int np, const void* us, const void* ub, void* out, c
   } else {
     DGD_DISPATCH_NP(np, stage_t<float, NP>(us, ub, out, elem, E, S, N, mode, cb, cg, R, sh, st));
   }
+}
+
+void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub, void* out,
+                         const int4* elem, int64_t E, const void* S, const void* F, const void* N,
+                         int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st) {
+#define DGD_PACKED_LAUNCH(T, GG)                                                                \
+  DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage_packed<T, NP, GG>), dim3((unsigned)sh.grid),  \
+                                         dim3(64 * sh.waves), 0, st, (const T*)us, (const T*)ub, \
+                                         (T*)out, elem, E, (const double*)S, (const double*)F,   \
+                                         (const double*)N, mode, cb, cg, R, sh.epw, sh.blocks,   \
+                                         sh.remap ? 1 : 0))
+  if (prec == 0 && G == 4) {
+    DGD_PACKED_LAUNCH(double, 4);
+  } else if (prec == 0) {
+    DGD_PACKED_LAUNCH(double, 2);
+  } else if (G == 4) {
+    DGD_PACKED_LAUNCH(float, 4);
+  } else {
+    DGD_PACKED_LAUNCH(float, 2);
+  }
+#undef DGD_PACKED_LAUNCH
 }
 
 void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4* elem, int64_t E,

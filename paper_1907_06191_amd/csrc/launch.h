@@ -30,6 +30,14 @@ void launch_stage(int prec, int np, const void* us, const void* ub, void* out, c
                   int64_t E, const void* S, const void* N, int mode, double cb, double cg, int R,
                   const Shape& sh, hipStream_t st);
 
+// Packed stage for R <= 64 / G right-hand sides (G = 4: R <= 16, G = 2:
+// R <= 32): G elements per wave.  Same modes 0 and 1 as launch_stage; F is
+// FP64 [2][3][np][np], the self-face blocks with S_{o,mask} = S_{o,7} -
+// sum_{f not in mask} F_{o,f}.  The shape counts groups of G elements.
+void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub, void* out,
+                         const int4* elem, int64_t E, const void* S, const void* F, const void* N,
+                         int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st);
+
 // P3 stage on matrix cores (FP32 state, R % 16 == 0, one element per wave:
 // the shape must have epw = 1), same modes and coefficients as
 // launch_stage, with a per-element FP64 mass correction.

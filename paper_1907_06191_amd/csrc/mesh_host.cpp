@@ -19,7 +19,8 @@
 
 namespace dgd {
 
-void build_mesh_host(double L, int N, const double* disks, int n_disks, int strip, MeshHost& m) {
+void build_mesh_host(double L, int N, const double* disks, int n_disks, int strip, int group,
+                     MeshHost& m) {
   m.L = L;
   m.N = N;
   m.h = L / N;
@@ -52,6 +53,15 @@ void build_mesh_host(double L, int N, const double* disks, int n_disks, int stri
       for (int i = s0; i < std::min(N, s0 + W); ++i)
         if (m.active_cell[(size_t)j * N + i]) rank[(size_t)j * N + i] = nc++;
   const int64_t E = 2 * nc;
+  // element of ranked cell r and orientation o: runs of `group` cells give
+  // their T0 first, then their T1 (group 1: T0, T1 per cell), so aligned
+  // runs of up to `group` elements share one orientation
+  const int64_t Gc = group < 1 ? 1 : group;
+  auto elem_of = [&](int64_t r, int o) -> int64_t {
+    const int64_t start = r / Gc * Gc;
+    const int64_t gsz = std::min<int64_t>(Gc, nc - start);
+    return 2 * start + o * gsz + (r - start);
+  };
   m.ci.resize(E);
   m.cj.resize(E);
   m.orient.resize(E);
@@ -67,14 +77,14 @@ void build_mesh_host(double L, int N, const double* disks, int n_disks, int stri
       const int64_t r = rank[(size_t)j * N + i];
       if (r < 0) continue;
       for (int o = 0; o < 2; ++o) {
-        const int64_t e = 2 * r + o;
+        const int64_t e = elem_of(r, o);
         m.ci[e] = i;
         m.cj[e] = j;
         m.orient[e] = (int8_t)o;
         for (int f = 0; f < 3; ++f) {
           const int64_t rn = cell_rank(i + off[o][f][0], j + off[o][f][1]);
           if (rn >= 0) {
-            m.nbr[e * 3 + f] = (int32_t)(2 * rn + (1 - o));
+            m.nbr[e * 3 + f] = (int32_t)elem_of(rn, 1 - o);
             ++nf;
           }
         }

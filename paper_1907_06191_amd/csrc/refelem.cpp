@@ -225,6 +225,7 @@ RefElem build_ref_elem(int p, double eta) {
 
   R.S.assign(2 * 8 * np * np, 0);
   R.Nb.assign(2 * 3 * np * np, 0);
+  R.Fs.assign(2 * 3 * np * np, 0);
   R.Mass.assign(2 * np * np, 0);
   R.Minv.assign(2 * np * np, 0);
   R.W.assign(2 * 6 * np, 0);
@@ -283,9 +284,13 @@ RefElem build_ref_elem(int p, double eta) {
     for (int f = 0; f < 3; ++f)
       for (int i = 0; i < np; ++i)
         for (int j = 0; j < np; ++j) {
-          double acc = 0;
-          for (int k = 0; k < np; ++k) acc += Mi[i * np + k] * Fn[f][k * np + j];
+          double acc = 0, accs = 0;
+          for (int k = 0; k < np; ++k) {
+            acc += Mi[i * np + k] * Fn[f][k * np + j];
+            accs += Mi[i * np + k] * Fs[f][k * np + j];
+          }
           R.Nb[((o * 3 + f) * np + i) * np + j] = -acc;
+          R.Fs[((o * 3 + f) * np + i) * np + j] = -accs;
         }
     for (int k = 0; k < np * np; ++k) {
       R.Mass[o * np * np + k] = M[k];

@@ -57,11 +57,11 @@ bool valid(const TuneParams& p) {
 
 }  // namespace
 
-std::string tune_key(int np, int prec, bool mfma, int R, int64_t E) {
+std::string tune_key(int np, int prec, const char* kernel, int R, int64_t E) {
   const int e2 = E > 0 ? (int)std::floor(std::log2((double)E)) : 0;
   std::ostringstream k;
   k << device_info().arch << "|np" << np << "|" << (prec == DGD_FP64 ? "fp64" : "fp32") << "|"
-    << (mfma ? "mfma" : "valu") << "|R" << R << "|E2^" << e2;
+    << kernel << "|R" << R << "|E2^" << e2;
   return k.str();
 }
 
@@ -73,41 +73,33 @@ bool tune_find(const std::string& key, TuneParams* out) {
   return true;
 }
 
-Shape tune_shape(const TuneParams& p, int64_t E) {
+Shape tune_shape(const TuneParams& p, int64_t units) {
   const int64_t grid = p.grid_per_cu > 0 ? (int64_t)p.grid_per_cu * device_info().cus : 0;
-  return element_shape(E, p.epw, p.waves, p.remap != 0, grid);
+  return element_shape(units, p.epw, p.waves, p.remap != 0, grid);
 }
 
-TuneParams tune_stage(const RunTarget& t, int R, bool mfma, void* a, void* b, const void* base,
+TuneParams tune_stage(const std::string& key, int64_t units, int prec, int64_t n_values,
+                      bool one_epw, void* a, void* b, const void* base, const StageLaunch& launch_one,
                       hipStream_t st) {
-  const int64_t n = t.E * t.np * (int64_t)R;
-  if (t.prec == DGD_FP64)
+  const int64_t n = n_values;
+  if (prec == DGD_FP64)
     launch_fill_random((double*)a, n, 0x5eedull, st);
   else
     launch_fill_random_f32((float*)a, n, 0x5eedull, st);
   DGD_HIP_CHECK(hipGetLastError());
   if (!base) base = a;
-  // The timed launch is the common stage (stages 2 and 3 of SSP-RK3): read
-  // the stage input and the base state, write the output,
-  //   out = base + 1/4 (u - base) + g L(u),
-  // with a small g, so the values stay bounded however many launches
-  // alternate between the two buffers.
-  const double g = 1e-3, cb = 0.25;
+  // Launches alternate between a and b (stage input -> output), each also
+  // reading `base`: the common stage shape (stages 2 and 3 of SSP-RK3).
   int flip = 0;
   auto launch = [&](const Shape& sh) {
     const void* src = flip ? b : a;
     void* dst = flip ? a : b;
     flip ^= 1;
-    if (mfma)
-      launch_stage_p3_mfma(src, base, dst, t.elem, t.E, t.Atab, t.Ctab, t.Wtab, t.wsum, 1, cb, g, R,
-                           sh, st);
-    else
-      launch_stage(t.prec == DGD_FP64 ? 0 : 1, t.np, src, base, dst, t.elem, t.E, t.S, t.N, 1, cb,
-                   g, R, sh, st);
+    launch_one(sh, src, base, dst);
   };
   Events ev;
   auto time_ms = [&](const TuneParams& p, int reps) {
-    const Shape sh = tune_shape(p, t.E);
+    const Shape sh = tune_shape(p, units);
     launch(sh);
     launch(sh);
     DGD_HIP_CHECK(hipEventRecord(ev.a, st));
@@ -123,7 +115,7 @@ TuneParams tune_stage(const RunTarget& t, int R, bool mfma, void* a, void* b, co
   std::vector<TuneParams> cand;
   const int epws_valu[] = {1, 2, 4};
   for (int epw : epws_valu) {
-    if (mfma && epw != 1) continue;  // the matrix-core kernel takes one element per wave
+    if (one_epw && epw != 1) continue;
     for (int waves : {1, 2, 4})
       for (int remap : {0, 1})
         for (int gpc : {0, 4, 8, 16}) {
@@ -157,7 +149,7 @@ TuneParams tune_stage(const RunTarget& t, int R, bool mfma, void* a, void* b, co
             [](const TuneParams& x, const TuneParams& y) { return x.ms < y.ms; });
   const TuneParams best = cand[0];
   std::lock_guard<std::mutex> lk(g_mu);
-  g_table[tune_key(t.np, t.prec, mfma, R, t.E)] = best;
+  g_table[key] = best;
   return best;
 }
 

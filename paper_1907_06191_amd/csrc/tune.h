@@ -4,11 +4,12 @@
 // element and right-hand side is computed by one lane, in a fixed order),
 // so the shape is a pure performance choice.  The tuner times every shape
 // of a small search space on the device and keeps the fastest per key:
-// device architecture, element size Np, state precision, kernel (VALU or
-// matrix core), number of right-hand sides, and the element count rounded
-// down to a power of two.
+// device architecture, element size Np, state precision, kernel (VALU,
+// packed VALU or matrix core), number of right-hand sides, and the element
+// count rounded down to a power of two.
 #pragma once
 
+#include <functional>
 #include <string>
 
 #include "dgd_internal.h"
@@ -24,16 +25,22 @@ struct TuneParams {
   double ms = 0;        // measured time of one stage launch
 };
 
-std::string tune_key(int np, int prec, bool mfma, int R, int64_t E);
+std::string tune_key(int np, int prec, const char* kernel, int R, int64_t E);
 bool tune_find(const std::string& key, TuneParams* out);
-Shape tune_shape(const TuneParams& p, int64_t E);
+// Shape over `units` work units (elements, or element groups of the packed
+// kernel).
+Shape tune_shape(const TuneParams& p, int64_t units);
 
-// Time every candidate shape of one stage launch of `t` over R right-hand
-// sides, using a and b (each E * np * R states) as scratch and reading
-// `base` (E * np * R states, finite, left unchanged; NULL: a is filled and
-// read as the base), store the fastest under its key and return it.
-// Synchronises the stream.
-TuneParams tune_stage(const RunTarget& t, int R, bool mfma, void* a, void* b, const void* base,
+// One launch of the kernel being tuned: out = stage(src, base).
+using StageLaunch = std::function<void(const Shape&, const void* src, const void* base, void* out)>;
+
+// Time every candidate shape of `launch` over `units` work units, using a
+// and b (n_values states of the given precision each) as scratch and
+// reading `base` (n_values finite states, left unchanged; NULL: a is filled
+// and read as the base); `one_epw`: the kernel takes one unit per wave.
+// Stores the fastest under `key` and returns it.  Synchronises the stream.
+TuneParams tune_stage(const std::string& key, int64_t units, int prec, int64_t n_values,
+                      bool one_epw, void* a, void* b, const void* base, const StageLaunch& launch,
                       hipStream_t st);
 
 std::string tune_export();

@@ -63,6 +63,7 @@ _sig("dgd_mesh_create", [ctypes.c_double, ctypes.c_int32, _c_dp, ctypes.c_int32,
 _sig("dgd_mesh_info", [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                        ctypes.POINTER(ctypes.c_int32), _c_dp])
 _sig("dgd_mesh_elements", [_vp, _vp, _vp, _vp])
+_sig("dgd_mesh_faces", [_vp, _vp])
 _sig("dgd_mesh_destroy", [_vp], None)
 _sig("dgd_operator_build", [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                             ctypes.c_double, ctypes.POINTER(_vp)])
@@ -197,6 +198,13 @@ def dgd_mesh_elements(mesh):
     o = np.zeros(n, dtype=np.int8)
     _check(_lib.dgd_mesh_elements(mesh, ci.ctypes.data, cj.ctypes.data, o.ctypes.data))
     return ci, cj, o
+
+
+def dgd_mesh_faces(mesh):
+    n = dgd_mesh_info(mesh)["n_active"]
+    nbr = np.zeros((n, 3), dtype=np.int32)
+    _check(_lib.dgd_mesh_faces(mesh, nbr.ctypes.data))
+    return nbr
 
 
 def dgd_mesh_destroy(mesh) -> None:

@@ -36,16 +36,18 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("name", ["box20-p1", "pack256-p3"])
-@pytest.mark.parametrize("strip", [0, 64, 24])
-def test_host_mesh_matches_oracle_mesh(name, strip):
+@pytest.mark.parametrize("strip,group", [(0, 1), (64, 1), (24, 1), (0, 4), (64, 4), (24, 3)])
+def test_host_mesh_matches_oracle_mesh(name, strip, group):
     from paper_1907_06191_amd import dgd
     c = config(name)
     g = make_geometry(c["L"], c["N"], c["geom_seed"], phi=c["phi"], n_disks=c["n_disks"])
     dgd.dgd_set_option("mesh_strip", strip)
+    dgd.dgd_set_option("mesh_group", group)
     try:
         m = dgd.Mesh(g.L, g.N, g.disks)
     finally:
         dgd.dgd_set_option("mesh_strip", 64)
+        dgd.dgd_set_option("mesh_group", 4)
     o = omesh.build_mesh(g.L, g.N, g.disks)
     info = m.info()
     assert info["n_active"] == o.n_elements
@@ -53,16 +55,37 @@ def test_host_mesh_matches_oracle_mesh(name, strip):
     assert info["n_components"] == o.n_components()
     assert abs(info["removed_fraction"] - o.removed_fraction()) < 1e-15
     ci, cj, ori = m.elements()
-    if strip == 0 or strip >= g.N:
+    if (strip == 0 or strip >= g.N) and group == 1:
         # plain row-major order is the oracle's own order
         assert (ci == o.cell_i).all() and (cj == o.cell_j).all() and (ori == o.orient).all()
+    # runs of `group` cells: T0 of the run's cells, then T1 of the same cells
+    E = ci.size
+    cells = (cj.astype(np.int64) * g.N + ci)[ori == 0]
+    start = 0
+    while start < E:
+        n = min(group, (E - start) // 2)
+        assert (ori[start:start + n] == 0).all() and (ori[start + n:start + 2 * n] == 1).all()
+        assert np.array_equal(ci[start:start + n], ci[start + n:start + 2 * n])
+        assert np.array_equal(cj[start:start + n], cj[start + n:start + 2 * n])
+        start += 2 * n
+    assert np.unique(cells).size == cells.size
+    # face neighbours: the same (cell, orientation) as the oracle's, face by face
+    nbr = dgd.dgd_mesh_faces(m.handle)
+    okey = {(int(a), int(b), int(t)): e for e, (a, b, t) in
+            enumerate(zip(o.cell_i, o.cell_j, o.orient))}
+    perm = np.array([okey[(int(a), int(b), int(t))] for a, b, t in zip(ci, cj, ori)])
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    onb = o.nbr[perm]
+    expect = np.where(onb >= 0, inv[np.maximum(onb, 0)], -1)
+    assert np.array_equal(nbr, expect)
     # same set of (cell, orientation), each once
     key = lambda i, j, t: (np.asarray(j, np.int64) * g.N + np.asarray(i)) * 2 + np.asarray(t)  # noqa: E731
     assert np.array_equal(np.sort(key(ci, cj, ori)), np.sort(key(o.cell_i, o.cell_j, o.orient)))
     if strip:
         w = strip
-        strip_of = ci // w
-        assert (np.diff(strip_of) >= 0).all()     # strips in order
+        strip_of = ci[ori == 0] // w
+        assert (np.diff(strip_of) >= 0).all()     # strips in order (cells in rank order)
 
 
 def test_host_mesh_edge_cases():

@@ -33,7 +33,7 @@ def _case(nrhs, N=64, seed=41):
     return g, pts
 
 
-@pytest.mark.parametrize("p,R,kernel", [(2, 64, "valu"), (1, 16, "valu"), (3, 16, "mfma")])
+@pytest.mark.parametrize("p,R,kernel", [(2, 64, "valu"), (1, 16, "packed"), (2, 32, "packed"), (3, 16, "mfma")])
 def test_autotune_shape_valid_and_bit_invariant(dgd, p, R, kernel):
     g, pts = _case(R)
     mesh = dgd.Mesh(g.L, g.N, g.disks)
