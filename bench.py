@@ -153,9 +153,11 @@ def plain(args):
     sbytes = 8 if prec == dgd.DGD_FP64 else 4
     bytes_per_launch = 8.0 * sbytes / 3.0 * dof
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
-    mfma = p == 3 and prec == dgd.DGD_FP32 and R % 16 == 0
-    kernel = "k_stage_p3_mfma" if mfma else f"k_stage<{'double' if sbytes == 8 else 'float'},{npn}>"
-    dtype = ("f32 MFMA contraction + f64 mass correction, f32 state" if mfma else
+    kind, shape = dgd.dgd_run_kernel(run.handle)
+    ts = "double" if sbytes == 8 else "float"
+    kernel = {"mfma": "k_stage_p3_mfma", "packed": f"k_stage_packed<{ts},{npn},{4 if R <= 16 else 2}>",
+              "valu": f"k_stage<{ts},{npn}>"}[kind]
+    dtype = ("f32 MFMA contraction + f64 mass correction, f32 state" if kind == "mfma" else
              ("f64 arithmetic, f32 state" if sbytes == 4 else "f64"))
     out = base_record(args, value, ms_per_step, dtype, {
         "workload": f"{args.workload}: plain solve, {g.N}x{g.N} grid on [0,{g.L:g}]^2 um, "
@@ -173,7 +175,7 @@ def plain(args):
     out["roofline"] = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
-        "bytes_per_launch": bytes_per_launch, "launch_ms": round(launch_ms, 5),
+        "bytes_per_launch": bytes_per_launch, "launch_ms": round(launch_ms, 5), "launch_shape": shape,
         "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated), "
                         "null unless measured on this kernel source"}
     run.close()

@@ -174,6 +174,13 @@ int dgd_run_moments(dgd_run* run, double* moments_out);
 int dgd_run_get_state(dgd_run* run, void* host_out);
 int dgd_run_set_state(dgd_run* run, const void* host_in);
 
+/* The stage kernel and launch shape the run uses: kernel 0 = one element
+ * and up to 64 right-hand sides per wave, 1 = several elements per wave
+ * (at most 32 right-hand sides), 2 = P3 on matrix cores; shape_out
+ * (nullable) [4] = (elements per wave, waves per workgroup, XCD band order,
+ * workgroups launched).  Errors: EINVAL. */
+int dgd_run_kernel(const dgd_run* run, int32_t* kernel_out, int64_t* shape_out);
+
 void dgd_run_destroy(dgd_run* run);
 
 /*
@@ -296,9 +303,11 @@ void dgd_surrogate_destroy(dgd_surrogate* s);
  *   "stage_waves"  waves per workgroup of the stage kernel, 1..4
  *   "xcd_remap"    1 = each XCD sweeps one contiguous band of elements
  *   "stage_grid"   > 0: persistent stage kernel with this many workgroups
- *   "p3_mfma"      1 = P3 stages with FP32 state run on matrix cores
- *                  (v_mfma_f32_16x16x4_f32, FP64 mass correction) when the
- *                  right-hand-side count is a multiple of 16
+ *   "p3_mfma"      P3 stages with FP32 state on matrix cores
+ *                  (v_mfma_f32_16x16x4_f32, FP64 mass correction; the
+ *                  right-hand-side count a multiple of 16): 0 = never,
+ *                  1 = always, 2 (default) = when the autotuner timed them
+ *                  faster than the VALU kernel for the run's key
  *   "mesh_strip"   element order of meshes created afterwards: vertical strips
  *                  of this many cell columns, each row-major (0 = plain rows)
  *   "mesh_group"   element order of meshes created afterwards: the ranked

@@ -41,7 +41,7 @@ struct Options {
   int mesh_strip = 64;      // element order: vertical strips of this many cell columns (0: rows)
   int mesh_group = 4;       // element order: runs of this many cells give their T0, then their T1
   bool packed = true;       // R <= 32: several elements per wave (packed stage kernel)
-  bool p3_mfma = true;      // P3 FP32 stages on matrix cores when R % 16 == 0
+  int p3_mfma = 2;          // P3 FP32 stages on matrix cores: 0 never, 1 always, 2 when faster
   bool autotune = true;     // tune the stage launch shape per key on first use
 };
 Options g_opt;
@@ -137,22 +137,21 @@ RunTarget plain_target(const dgd_op* op) {
   return t;
 }
 
-// Whether a stage on (E, R) takes the P3 matrix-core kernel.
-bool use_p3_mfma(const RunTarget& t, int R) {
-  return g_opt.p3_mfma && t.Atab && t.prec == DGD_FP32 && t.np == 10 && R % 16 == 0 &&
+// Whether the P3 matrix-core kernel can run a stage on (t, R).
+bool mfma_possible(const RunTarget& t, int R) {
+  return t.Atab && t.prec == DGD_FP32 && t.np == 10 && R % 16 == 0 &&
          (double)t.E * 10.0 * (double)R < 2147483647.0;
 }
 
-// The stage kernel a run of (t, R) uses: matrix cores for P3 FP32 when R
-// is a multiple of 16; for R <= 32 the packed kernel (several elements per
-// wave); else one element and up to 64 right-hand sides per wave.
+// Stage kernels: one element and up to 64 right-hand sides per wave
+// (VALU); for R <= 32 several elements per wave (packed); P3 FP32 with R a
+// multiple of 16 on matrix cores (mfma).
 enum StageKind { kValu = 0, kPacked = 1, kMfma = 2 };
 const char* const kKindName[3] = {"valu", "packed", "mfma"};
 
-StageKind stage_kind(const RunTarget& t, int R) {
-  if (use_p3_mfma(t, R)) return kMfma;
-  if (g_opt.packed && t.F && R <= 32) return kPacked;
-  return kValu;
+// The VALU kernel for (t, R): packed when R <= 32.
+StageKind valu_kind(const RunTarget& t, int R) {
+  return g_opt.packed && t.F && R <= 32 ? kPacked : kValu;
 }
 
 int packed_group(int R) { return R <= 16 ? 4 : 2; }
@@ -165,6 +164,23 @@ int64_t stage_units(const RunTarget& t, int R, StageKind k) {
   return (t.E + G - 1) / G;
 }
 
+std::string kind_key(const RunTarget& t, int R, StageKind k) {
+  return tune_key(t.np, t.prec, kKindName[k], R, t.E);
+}
+
+// The kernel for (t, R) without timing: the matrix cores when forced
+// ("p3_mfma" 1), else the faster of the tuned kinds when both are in the
+// table ("p3_mfma" 2, autotuning on), else the VALU kernel.
+StageKind stage_kind(const RunTarget& t, int R) {
+  const StageKind v = valu_kind(t, R);
+  if (!mfma_possible(t, R) || g_opt.p3_mfma == 0) return v;
+  if (g_opt.p3_mfma == 1) return kMfma;
+  TuneParams pm, pv;
+  if (g_opt.autotune && tune_find(kind_key(t, R, kMfma), &pm) && tune_find(kind_key(t, R, v), &pv))
+    return pm.ms < pv.ms ? kMfma : v;
+  return v;
+}
+
 // Launch shape of the stage kernel of `kind` on (t, R): the tuned one for
 // its key when autotuning is on and the key has been tuned, else the
 // options.
@@ -172,16 +188,14 @@ Shape pick_shape(const RunTarget& t, int R, StageKind kind) {
   const int64_t units = stage_units(t, R, kind);
   if (g_opt.autotune) {
     TuneParams p;
-    if (tune_find(tune_key(t.np, t.prec, kKindName[kind], R, t.E), &p)) return tune_shape(p, units);
+    if (tune_find(kind_key(t, R, kind), &p)) return tune_shape(p, units);
   }
-  return element_shape(units, kind == kMfma ? 1 : g_opt.stage_epw, g_opt.stage_waves,
-                       g_opt.xcd_remap, g_opt.stage_grid);
+  return element_shape(units, g_opt.stage_epw, g_opt.stage_waves, g_opt.xcd_remap, g_opt.stage_grid);
 }
-Shape pick_shape(const RunTarget& t, int R) { return pick_shape(t, R, stage_kind(t, R)); }
 
-void stage(const RunTarget& t, const Shape& sh, const void* us, const void* ub, void* out, int mode,
-           double cb, double cg, int R, hipStream_t st) {
-  switch (stage_kind(t, R)) {
+void stage(const RunTarget& t, StageKind kind, const Shape& sh, const void* us, const void* ub,
+           void* out, int mode, double cb, double cg, int R, hipStream_t st) {
+  switch (kind) {
     case kMfma:
       launch_stage_p3_mfma(us, ub, out, t.elem, t.E, t.Atab, t.Ctab, t.Wtab, t.wsum, mode, cb, cg,
                            R, sh, st);
@@ -196,24 +210,37 @@ void stage(const RunTarget& t, const Shape& sh, const void* us, const void* ub, 
   }
 }
 
-// Tune the stage launch shape of (t, R) with a and b as scratch (and base
-// read, NULL: a): the common stage out = base + 1/4 (u - base) + g L(u)
-// with a small g, so the values stay bounded over the timed launches.
-TuneParams tune_target(const RunTarget& t, int R, void* a, void* b, const void* base,
-                       hipStream_t st) {
-  const StageKind kind = stage_kind(t, R);
-  const std::string key = tune_key(t.np, t.prec, kKindName[kind], R, t.E);
+// Tune the launch shape of the stage kernel `kind` on (t, R) with a and b
+// as scratch (and base read, NULL: a): the common stage
+// out = base + 1/4 (u - base) + g L(u) with a small g, so the values stay
+// bounded over the timed launches.
+TuneParams tune_kind(const RunTarget& t, int R, StageKind kind, void* a, void* b, const void* base,
+                     hipStream_t st) {
   auto one = [&](const Shape& sh, const void* src, const void* bs, void* dst) {
-    stage(t, sh, src, bs, dst, 1, 0.25, 1e-3, R, st);
+    stage(t, kind, sh, src, bs, dst, 1, 0.25, 1e-3, R, st);
   };
-  return tune_stage(key, stage_units(t, R, kind), t.prec, t.E * t.np * (int64_t)R, kind == kMfma,
-                    a, b, base, one, st);
+  return tune_stage(kind_key(t, R, kind), stage_units(t, R, kind), t.prec,
+                    t.E * t.np * (int64_t)R, a, b, base, one, st);
+}
+
+// Tune every kernel kind that may run (t, R) whose key is not yet in the
+// table (force: tune them again); returns the kind stage_kind then picks.
+StageKind tune_target(const RunTarget& t, int R, void* a, void* b, const void* base,
+                      hipStream_t st, bool force) {
+  std::vector<StageKind> kinds{valu_kind(t, R)};
+  if (mfma_possible(t, R) && g_opt.p3_mfma != 0) kinds.push_back(kMfma);
+  if (g_opt.p3_mfma == 1 && mfma_possible(t, R)) kinds = {kMfma};
+  for (StageKind k : kinds) {
+    TuneParams p;
+    if (force || !tune_find(kind_key(t, R, k), &p)) tune_kind(t, R, k, a, b, base, st);
+  }
+  return stage_kind(t, R);
 }
 
 // Tables of the P3 matrix-core kernel: for class (o, mask) the stacked
 // stencil matrix A = [S | N_0 | N_1 | N_2] (10 x 40, missing faces zero,
 // rows 10..15 zero), in FP32 and in the lane order of v_mfma_f32_16x16x4
-// (lane l, step s holds A[l % 16][4 s + l / 16]); C = w^T A in FP64 with
+// (lane l, step s holds A[l % 16][4 s + l / 16], stored [class][s][lane]); C = w^T A in FP64 with
 // w the row sums of the reference mass matrix; W = w padded to 16.
 void build_p3_tables(dgd_op* op) {
   const RefElem& R = op->ref;
@@ -242,8 +269,10 @@ void build_p3_tables(dgd_op* op) {
         for (int m = 0; m < np; ++m) c += w[m] * A[m * 40 + k];
         Ct[cls * 40 + k] = c;
       }
-      for (int l = 0; l < 64; ++l)
-        for (int s = 0; s < 10; ++s) At[(cls * 64 + l) * 10 + s] = (float)A[(l % 16) * 40 + 4 * s + l / 16];
+      // [cls][s][lane]: the ten operand loads of a wave are each one
+      // contiguous 256-byte row
+      for (int s = 0; s < 10; ++s)
+        for (int l = 0; l < 64; ++l) At[(cls * 10 + s) * 64 + l] = (float)A[(l % 16) * 40 + 4 * s + l / 16];
     }
   }
   op->d_Atab = (float*)upload(At);
@@ -386,12 +415,9 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
                                  hipMemcpyHostToDevice, run->stream));
     // the stage launch shape, tuned on first use of its key (the two stage
     // buffers are free until the first step)
-    if (g_opt.autotune) {
-      TuneParams p;
-      if (!tune_find(tune_key(t.np, t.prec, kKindName[stage_kind(t, R)], R, t.E), &p))
-        tune_target(t, R, run->U1, run->U2, run->U, run->stream);
-    }
-    run->sh = pick_shape(t, R);
+    if (g_opt.autotune) tune_target(t, R, run->U1, run->U2, run->U, run->stream, false);
+    run->kind = (int)stage_kind(t, R);
+    run->sh = pick_shape(t, R, (StageKind)run->kind);
     const Shape shr = reduce_shape(t.E);
     launch_ic_mass(t.np, t.elem, t.E, t.quad, t.nq, run->d_x0, t.blk_geom, sigma0, t.h, kCutoff, R,
                    shr, run->d_part, run->stream);
@@ -420,9 +446,11 @@ void run_stage_steps(dgd_run* run, int64_t n, double dt) {
   for (int64_t s = 0; s < n; ++s) {
     // Shu-Osher SSP-RK3 as corrections of u^n:
     //   u1 = u + dt L u;  u2 = u + 1/4 (u1 - u) + 1/4 dt L u1;  u' = u + 2/3 (u2 - u) + 2/3 dt L u2
-    stage(t, run->sh, run->U, nullptr, run->U1, 1, 0.0, gam, run->R, run->stream);
-    stage(t, run->sh, run->U1, run->U, run->U2, 1, 0.25, 0.25 * gam, run->R, run->stream);
-    stage(t, run->sh, run->U2, run->U, run->U, 1, 2.0 / 3.0, 2.0 / 3.0 * gam, run->R, run->stream);
+    const StageKind k = (StageKind)run->kind;
+    stage(t, k, run->sh, run->U, nullptr, run->U1, 1, 0.0, gam, run->R, run->stream);
+    stage(t, k, run->sh, run->U1, run->U, run->U2, 1, 0.25, 0.25 * gam, run->R, run->stream);
+    stage(t, k, run->sh, run->U2, run->U, run->U, 1, 2.0 / 3.0, 2.0 / 3.0 * gam, run->R,
+          run->stream);
   }
 }
 
@@ -627,7 +655,8 @@ int dgd_set_option(const char* name, int64_t value) {
       if (value < 0 || value > (1 << 24)) fail(DGD_EINVAL, "stage_grid must be in [0, 2^24]");
       g_opt.stage_grid = value;
     } else if (n == "p3_mfma") {
-      g_opt.p3_mfma = value != 0;
+      if (value < 0 || value > 2) fail(DGD_EINVAL, "p3_mfma must be 0, 1 or 2");
+      g_opt.p3_mfma = (int)value;
     } else if (n == "mesh_strip") {
       if (value < 0 || value > 16384) fail(DGD_EINVAL, "mesh_strip must be in [0, 16384]");
       g_opt.mesh_strip = (int)value;
@@ -661,7 +690,10 @@ int dgd_autotune(dgd_op* op, int32_t n_points, void* hip_stream, int32_t* shape_
       launch_fill_random((double*)c, n, 0xba5eull, (hipStream_t)hip_stream);
     else
       launch_fill_random_f32((float*)c, n, 0xba5eull, (hipStream_t)hip_stream);
-    const TuneParams p = tune_target(t, n_points, a, b, c, (hipStream_t)hip_stream);
+    tune_target(t, n_points, a, b, c, (hipStream_t)hip_stream, true);
+    const StageKind kind = stage_kind(t, n_points);
+    TuneParams p;
+    if (!tune_find(kind_key(t, n_points, kind), &p)) fail(DGD_EDEVICE, "tuning left no entry");
     if (shape_out) {
       shape_out[0] = p.epw;
       shape_out[1] = p.waves;
@@ -885,7 +917,8 @@ int dgd_operator_apply(dgd_op* op, const void* d_in, void* d_out, int32_t n_rhs,
     if (d_in == d_out) fail(DGD_EINVAL, "input and output must not overlap");
     const double h = op->mesh->host.h;
     const RunTarget t = plain_target(op);
-    stage(t, pick_shape(t, n_rhs), d_in, nullptr, d_out, 0, 0.0, op->D / (h * h), n_rhs,
+    const StageKind kind = stage_kind(t, n_rhs);
+    stage(t, kind, pick_shape(t, n_rhs, kind), d_in, nullptr, d_out, 0, 0.0, op->D / (h * h), n_rhs,
           (hipStream_t)hip_stream);
     DGD_HIP_CHECK(hipGetLastError());
     return DGD_OK;
@@ -955,6 +988,20 @@ int dgd_run_set_state(dgd_run* run, const void* host_in) {
     const size_t n = (size_t)run->t.E * run->t.np * run->R * state_bytes(run->t.prec);
     DGD_HIP_CHECK(hipMemcpyAsync(run->U, host_in, n, hipMemcpyHostToDevice, run->stream));
     DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+    return DGD_OK;
+  });
+}
+
+int dgd_run_kernel(const dgd_run* run, int32_t* kernel_out, int64_t* shape_out) {
+  return guarded([&]() -> int {
+    if (!run) fail(DGD_EINVAL, "run is NULL");
+    if (kernel_out) *kernel_out = run->kind;
+    if (shape_out) {
+      shape_out[0] = run->sh.epw;
+      shape_out[1] = run->sh.waves;
+      shape_out[2] = run->sh.remap ? 1 : 0;
+      shape_out[3] = run->sh.grid;
+    }
     return DGD_OK;
   });
 }

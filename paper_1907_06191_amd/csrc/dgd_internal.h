@@ -92,7 +92,7 @@ struct dgd_op {
   int nq = 0;
   // P3 matrix-core path (FP32 state): A operands in lane order, FP64 flux
   // coefficients and mass-row weights (see the MFMA stage kernel)
-  float* d_Atab = nullptr;   // [16][64][10]
+  float* d_Atab = nullptr;   // [16][10][64]
   double* d_Ctab = nullptr;  // [16][40]
   double* d_Wtab = nullptr;  // [2][16]
   double wsum = 0;
@@ -142,6 +142,7 @@ struct dgd_run {
   double* d_mom = nullptr;    // [G][R][6]
   int* d_blk_start = nullptr; // [G + 1] (plain runs: {0, nblk_red})
   dgd::Shape sh;              // stage launch shape
+  int kind = 0;               // stage kernel (VALU, packed, matrix cores)
   std::vector<double> x0;
   double t_ms = 0;
   // captured step graphs keyed by (dt bits, steps)

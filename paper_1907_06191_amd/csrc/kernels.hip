@@ -222,88 +222,119 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
 // A[m = l % 16][k = 4 s + l / 16] and B[k = 4 s + l / 16][n = l % 16] and
 // receives D[m = 4 (l / 16) + i][n = l % 16], i < 4.
 //
+// A wave covers 64 right-hand sides of an element (blockIdx.y selects which
+// 64).  Lane (q, n) = (l / 16, l % 16) loads the four consecutive columns
+// 4n .. 4n+3 of stencil row 4 s + q as one 16-byte load, so each step's
+// loads are four whole 256-byte rows; the four 16-column blocks are
+// t = 0..3 with block t holding columns {4n + t}: the t-th component of
+// every lane's load is exactly that block's B operand, and the four blocks'
+// results for a row are again four consecutive columns, stored as one
+// 16-byte store.
+//
 // FP32 products lose mass systematically over 10^6 steps, so each column's
 // result is corrected by a constant so that its mass w^T L(u) equals the
 // FP64 sum of the face fluxes, Phi = C_{o,mask} . u_stencil, with the flux
 // coefficients C = w^T [S | N...] (w = reference mass-matrix row sums).
-// Atab: [16 classes][64 lanes][10] float; Ctab: [16][40] double;
-// Wtab: [2][16] double (row weights, zero beyond 10); wsum = sum of w.
+// Atab: [16 classes][10 steps][64 lanes] float; Ctab: [16][40] double;
+// Wtab: [2][16] double (row weights, zero beyond 10); inv_wsum = 1 / sum w.
 __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__ us, const float* ub,
                                                        float* out, const int4* __restrict__ elem,
                                                        int64_t E, const float* __restrict__ Atab,
                                                        const double* __restrict__ Ctab,
-                                                       const double* __restrict__ Wtab, double wsum,
-                                                       int mode, double cb, double cg, int R,
-                                                       int64_t nblocks, int remap) {
+                                                       const double* __restrict__ Wtab,
+                                                       double inv_wsum, int mode, double cb,
+                                                       double cg, int R, int epw, int64_t nblocks,
+                                                       int remap) {
   typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int q = lane >> 4, n = lane & 15;
   const bool use_base = ub != nullptr;
+  // this lane's four columns; R % 16 == 0, so they are all in range or all
+  // out (then a valid column is read and nothing is stored)
+  const int c_raw = blockIdx.y * WAVE + 4 * n;
+  const bool col_live = c_raw < R;
+  const uint32_t col = (uint32_t)(col_live ? c_raw : 0);
   const BlockIter it = block_iter(nblocks, remap);
   for (int64_t b = it.first; b < it.end; b += it.stride) {
-    const int64_t e = b * (blockDim.x / WAVE) + w;
-    if (e >= E) continue;
-    const int4 m = elem[e];
-    const int o = m.w & 1;
-    const int mask = (m.w >> 1) & 7;
-    const int cls = o * 8 + mask;
-    // per-lane stencil offsets (element, node) for k = 4 s + q; the host
-    // guarantees E * 10 * R < 2^31
-    uint32_t koff[10];
-    float a[10];
-    double cf[10];
-#pragma unroll
-    for (int s = 0; s < 10; ++s) {
-      const int k = 4 * s + q;
-      const int blk = k / 10, j = k % 10;
-      int eb = (int)e;
-      if (blk == 1 && m.x >= 0) eb = m.x;
-      if (blk == 2 && m.y >= 0) eb = m.y;
-      if (blk == 3 && m.z >= 0) eb = m.z;
-      koff[s] = ((uint32_t)eb * 10u + (uint32_t)j) * (uint32_t)R + (uint32_t)n;
-      a[s] = Atab[((int64_t)cls * WAVE + lane) * 10 + s];
-      cf[s] = Ctab[cls * 40 + k];
-    }
-    double wr[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) wr[i] = Wtab[o * 16 + 4 * q + i];
-    const uint32_t self = (uint32_t)e * 10u * (uint32_t)R;
-    for (int c0 = 0; c0 < R; c0 += 16) {
-      const int col = c0 + n;
-      const float c = us[self + (uint32_t)col];
-      float v[10];
-#pragma unroll
-      for (int s = 0; s < 10; ++s) v[s] = us[koff[s] + (uint32_t)c0];
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      double phi = 0.0;
+    const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
+    const int64_t e1 = e0 + epw < E ? e0 + epw : E;
+    for (int64_t e = e0; e < e1; ++e) {
+      const int4 m = elem[e];
+      const int o = m.w & 1;
+      const int mask = (m.w >> 1) & 7;
+      const int cls = o * 8 + mask;
+      const uint32_t self = (uint32_t)e * 10u * (uint32_t)R;
+      // every load first: pivot row, the ten operand rows (stencil rows
+      // 4 s + q, the host guarantees E * 10 * R < 2^31), the own rows this
+      // lane writes (u and base), the class's operator entries
+      f32x4 cpv = *(const f32x4*)(us + self + col);
+      f32x4 v[10];
+      float a[10];
+      double cf[10];
 #pragma unroll
       for (int s = 0; s < 10; ++s) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], v[s] - c, acc, 0, 0, 0);
-        phi = fma(cf[s], (double)v[s], phi);
+        const int k = 4 * s + q;
+        const int blk = k / 10, j = k % 10;
+        int eb = (int)e;
+        if (blk == 1 && m.x >= 0) eb = m.x;
+        if (blk == 2 && m.y >= 0) eb = m.y;
+        if (blk == 3 && m.z >= 0) eb = m.z;
+        v[s] = *(const f32x4*)(us + ((uint32_t)eb * 10u + (uint32_t)j) * (uint32_t)R + col);
+        a[s] = Atab[(cls * 10 + s) * WAVE + lane];
+        cf[s] = Ctab[cls * 40 + k];
       }
-      double wa = 0.0;
+      f32x4 u0[4], b0[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) wa = fma(wr[i], (double)acc[i], wa);
-      phi += __shfl_xor(phi, 16);
-      phi += __shfl_xor(phi, 32);
-      wa += __shfl_xor(wa, 16);
-      wa += __shfl_xor(wa, 32);
-      const double alpha = (phi - wa) / wsum;
+      for (int i = 0; i < 4; ++i) {
+        const int row = 4 * q + i;
+        const uint32_t idx = self + (uint32_t)(row < 10 ? row : 0) * (uint32_t)R + col;
+        if (mode != 0) {
+          u0[i] = *(const f32x4*)(us + idx);
+          b0[i] = use_base ? *(const f32x4*)(ub + idx) : u0[i];
+        }
+      }
+      double wr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) wr[i] = Wtab[o * 16 + 4 * q + i];
+      f32x4 acc[4];
+      double alpha[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        f32x4 d = {0.f, 0.f, 0.f, 0.f};
+        double phi = 0.0;
+#pragma unroll
+        for (int s = 0; s < 10; ++s) {
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], v[s][t] - cpv[t], d, 0, 0, 0);
+          phi = fma(cf[s], (double)v[s][t], phi);
+        }
+        double dl = phi;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dl = fma(-wr[i], (double)d[i], dl);
+        dl += __shfl_xor(dl, 16);
+        dl += __shfl_xor(dl, 32);
+        acc[t] = d;
+        alpha[t] = dl * inv_wsum;
+      }
+      if (!col_live) continue;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = 4 * q + i;
         if (row >= 10) continue;
-        const uint32_t idx = self + (uint32_t)(row * R + col);
-        const double val = (double)acc[i] + alpha;
-        if (mode == 0) {
-          out[idx] = (float)(cg * val);
-        } else {
-          const double u0 = (double)us[idx];
-          const double b0 = use_base ? (double)ub[idx] : u0;
-          out[idx] = round_stochastic(b0 + cb * (u0 - b0) + cg * val,
-                                      state_salt(m.w, row * R + col));
+        const uint32_t idx = self + (uint32_t)row * (uint32_t)R + col;
+        f32x4 r4;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const double val = (double)acc[t][i] + alpha[t];
+          if (mode == 0) {
+            r4[t] = (float)(cg * val);
+          } else {
+            const double uu = (double)u0[i][t], bb = (double)b0[i][t];
+            r4[t] = round_stochastic(bb + cb * (uu - bb) + cg * val,
+                                     state_salt(m.w, row * R + (int)col + t));
+          }
         }
+        *(f32x4*)(out + idx) = r4;
       }
     }
   }
@@ -802,9 +833,10 @@ void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub
 void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4* elem, int64_t E,
                           const float* Atab, const double* Ctab, const double* Wtab, double wsum,
                           int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st) {
-  hipLaunchKernelGGL(k_stage_p3_mfma, dim3((unsigned)sh.grid), dim3(64 * sh.waves), 0, st,
-                     (const float*)us, (const float*)ub, (float*)out, elem, E, Atab, Ctab, Wtab, wsum,
-                     mode, cb, cg, R, sh.blocks, sh.remap ? 1 : 0);
+  const dim3 grid((unsigned)sh.grid, (unsigned)((R + WAVE - 1) / WAVE));
+  hipLaunchKernelGGL(k_stage_p3_mfma, grid, dim3(64 * sh.waves), 0, st, (const float*)us,
+                     (const float*)ub, (float*)out, elem, E, Atab, Ctab, Wtab, 1.0 / wsum, mode, cb,
+                     cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0);
 }
 
 void launch_cheb(int np, const double* tcur, const double* tprev, double* tnext, double* res,

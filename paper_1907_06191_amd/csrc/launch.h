@@ -38,9 +38,9 @@ void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub
                          const int4* elem, int64_t E, const void* S, const void* F, const void* N,
                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st);
 
-// P3 stage on matrix cores (FP32 state, R % 16 == 0, one element per wave:
-// the shape must have epw = 1), same modes and coefficients as
-// launch_stage, with a per-element FP64 mass correction.
+// P3 stage on matrix cores (FP32 state, R % 16 == 0; each wave walks epw
+// elements for 64 right-hand sides, grid.y covers the rest), same modes and
+// coefficients as launch_stage, with a per-element FP64 mass correction.
 void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4* elem, int64_t E,
                           const float* Atab, const double* Ctab, const double* Wtab, double wsum,
                           int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st);

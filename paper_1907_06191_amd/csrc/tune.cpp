@@ -78,9 +78,8 @@ Shape tune_shape(const TuneParams& p, int64_t units) {
   return element_shape(units, p.epw, p.waves, p.remap != 0, grid);
 }
 
-TuneParams tune_stage(const std::string& key, int64_t units, int prec, int64_t n_values,
-                      bool one_epw, void* a, void* b, const void* base, const StageLaunch& launch_one,
-                      hipStream_t st) {
+TuneParams tune_stage(const std::string& key, int64_t units, int prec, int64_t n_values, void* a,
+                      void* b, const void* base, const StageLaunch& launch_one, hipStream_t st) {
   const int64_t n = n_values;
   if (prec == DGD_FP64)
     launch_fill_random((double*)a, n, 0x5eedull, st);
@@ -113,9 +112,7 @@ TuneParams tune_stage(const std::string& key, int64_t units, int prec, int64_t n
   };
 
   std::vector<TuneParams> cand;
-  const int epws_valu[] = {1, 2, 4};
-  for (int epw : epws_valu) {
-    if (one_epw && epw != 1) continue;
+  for (int epw : {1, 2, 4}) {
     for (int waves : {1, 2, 4})
       for (int remap : {0, 1})
         for (int gpc : {0, 4, 8, 16}) {

@@ -37,11 +37,10 @@ using StageLaunch = std::function<void(const Shape&, const void* src, const void
 // Time every candidate shape of `launch` over `units` work units, using a
 // and b (n_values states of the given precision each) as scratch and
 // reading `base` (n_values finite states, left unchanged; NULL: a is filled
-// and read as the base); `one_epw`: the kernel takes one unit per wave.
-// Stores the fastest under `key` and returns it.  Synchronises the stream.
-TuneParams tune_stage(const std::string& key, int64_t units, int prec, int64_t n_values,
-                      bool one_epw, void* a, void* b, const void* base, const StageLaunch& launch,
-                      hipStream_t st);
+// and read as the base).  Stores the fastest under `key` and returns it.
+// Synchronises the stream.
+TuneParams tune_stage(const std::string& key, int64_t units, int prec, int64_t n_values, void* a,
+                      void* b, const void* base, const StageLaunch& launch, hipStream_t st);
 
 std::string tune_export();
 int tune_import(const std::string& text);

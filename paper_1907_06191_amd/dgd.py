@@ -78,6 +78,7 @@ _sig("dgd_run_advance", [_vp, ctypes.c_int64, ctypes.c_double])
 _sig("dgd_run_moments", [_vp, _c_dp])
 _sig("dgd_run_get_state", [_vp, _vp])
 _sig("dgd_run_set_state", [_vp, _vp])
+_sig("dgd_run_kernel", [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)])
 _sig("dgd_run_destroy", [_vp], None)
 _sig("dgd_batch_workspace_size", [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)])
 _sig("dgd_batch_create", [_vp, ctypes.c_int32, _c_dp, ctypes.c_int32, ctypes.c_double, _vp, ctypes.c_size_t,
@@ -278,6 +279,17 @@ def dgd_run_get_state(run, n_values: int, dtype) -> np.ndarray:
 def dgd_run_set_state(run, state: np.ndarray) -> None:
     s = np.ascontiguousarray(state)
     _check(_lib.dgd_run_set_state(run, s.ctypes.data))
+
+
+KERNEL_NAMES = ("valu", "packed", "mfma")
+
+
+def dgd_run_kernel(run):
+    """(kernel name, dict(epw, waves, xcd_remap, grid)) of the run's stage launches."""
+    k = ctypes.c_int32()
+    sh = (ctypes.c_int64 * 4)()
+    _check(_lib.dgd_run_kernel(run, ctypes.byref(k), sh))
+    return KERNEL_NAMES[k.value], dict(epw=sh[0], waves=sh[1], xcd_remap=sh[2], grid=sh[3])
 
 
 def dgd_run_destroy(run) -> None:

@@ -260,8 +260,12 @@ def test_p3_mfma_operator_extraction(dgd):
     x = torch.zeros((n, R), dtype=torch.float32, device="cuda")
     x[:, :n] = torch.eye(n, dtype=torch.float32, device="cuda")
     y = torch.zeros_like(x)
-    op.apply(x, y, R)
-    torch.cuda.synchronize()
+    dgd.dgd_set_option("p3_mfma", 1)
+    try:
+        op.apply(x, y, R)
+        torch.cuda.synchronize()
+    finally:
+        dgd.dgd_set_option("p3_mfma", 2)
     Lg = y[:, :n].double().cpu().numpy()
     ci, cj, ori = mesh.elements()
     key = {(int(a), int(b), int(c)): e for e, (a, b, c) in enumerate(zip(m.cell_i, m.cell_j, m.orient))}
@@ -294,12 +298,13 @@ def test_p3_mfma_solve_matches_valu_and_oracle(dgd):
     ref = osolve.solve(prob, pts, 0.3, deltas, method="cheb")
     mesh = dgd.Mesh(g.L, g.N, g.disks)
     op = dgd.Operator(mesh, 3, 2.0, 10.0, dgd.DGD_FP32, dt_max_ms=dt)
-    sig_m, mom_m = op.solve(pts, 0.3, deltas)
-    dgd.dgd_set_option("p3_mfma", 0)
     try:
+        dgd.dgd_set_option("p3_mfma", 1)
+        sig_m, mom_m = op.solve(pts, 0.3, deltas)
+        dgd.dgd_set_option("p3_mfma", 0)
         sig_v, mom_v = op.solve(pts, 0.3, deltas)
     finally:
-        dgd.dgd_set_option("p3_mfma", 1)
+        dgd.dgd_set_option("p3_mfma", 2)
     e_ref = omom.rel_err(sig_m, omom.sigma_a(ref)).max()
     e_valu = omom.rel_err(sig_m, sig_v).max()
     drift = np.abs(mom_m[..., 0] - 1).max()
