@@ -169,6 +169,17 @@ int dgd_run_advance(dgd_run* run, int64_t n_steps, double dt_ms);
  * filled either way. */
 int dgd_run_moments(dgd_run* run, double* moments_out);
 
+/* Narrow-pulse q-space signal of the propagator of each start point (the
+ * propagator of section 1; its Fourier transform is the diffusion-weighted
+ * signal named in section 5):
+ *   E(q) = int u(x) exp(i q . (x - x0)) dx,
+ * q in rad/um (no 2 pi).  q: host float64 [n_q][2]; |q| h <= 4 per wave
+ * vector.  signal_out: host float64 [n_points][n_q][2] = (re, im).  Element
+ * integrals by a 12 x 12 collapsed Gauss-Legendre rule (exact to rounding
+ * for |q| h <= 4), FP64 phases from integer cell indices.  Plain runs only
+ * (EINVAL for a batch).  Synchronises the run's stream. */
+int dgd_run_signal(dgd_run* run, const double* q, int32_t n_q, double* signal_out);
+
 /* Copy the state to or from the host (checkpoint / resume); host buffer of
  * n_active * np * n_points values of the op's state type.  Synchronous. */
 int dgd_run_get_state(dgd_run* run, void* host_out);
@@ -197,6 +208,16 @@ void dgd_run_destroy(dgd_run* run);
 int dgd_eap_solve(dgd_op* op, const double* points, int32_t n_points, double sigma0_um,
                   const double* deltas_ms, int32_t n_deltas, double* sigma_out,
                   double* moments_out, void* d_ws, size_t ws_bytes, void* hip_stream);
+
+/* dgd_eap_solve with the q-space signal (dgd_run_signal) at every Delta:
+ *   signal_out: host float64 [n_points][n_deltas][n_q][2];
+ *   moments_out: NULL or host float64 [n_points][n_deltas][6] as in
+ *   dgd_eap_solve.
+ * Errors: as dgd_eap_solve and dgd_run_signal. */
+int dgd_eap_solve_signal(dgd_op* op, const double* points, int32_t n_points, double sigma0_um,
+                         const double* deltas_ms, int32_t n_deltas, const double* q, int32_t n_q,
+                         double* signal_out, double* moments_out, void* d_ws, size_t ws_bytes,
+                         void* hip_stream);
 
 /*
  * Whole solve with the exact semi-discrete flow instead of SSP-RK3: for each

@@ -127,6 +127,7 @@ RunTarget plain_target(const dgd_op* op) {
   t.W = op->d_W;
   t.Minv = op->d_Minv;
   t.quad = op->d_quad;
+  t.quad_host = op->quad.data();
   t.nq = op->nq;
   t.G = 1;
   t.nblk_red = reduce_shape(t.E).blocks;
@@ -518,6 +519,58 @@ int run_moments(dgd_run* run, double* out, std::string* why) {
   return DGD_OK;
 }
 
+constexpr double kSignalMaxQH = 4.0;   // |q| h bound of the element rule (error < 1e-16)
+
+// q-space signal of a plain run's current state: out [R][nq][2] = (re, im)
+// of int u exp(i q.(x - x0)) dx.  Element integrals of the nodal basis
+// times exp(i q.(x - c_K)) use the 12 x 12 collapsed Gauss-Legendre rule of
+// the initial data (exact to rounding for |q| h <= 4).
+void run_signal(dgd_run* run, const double* q, int nq, double* out) {
+  const RunTarget& t = run->t;
+  if (t.G != 1) fail(DGD_EINVAL, "the signal is computed for plain runs");
+  const int np = t.np, R = run->R;
+  std::vector<double> W((size_t)nq * 2 * np * 2, 0.0);
+  for (int k = 0; k < nq; ++k) {
+    const double qx = q[2 * k], qy = q[2 * k + 1];
+    if (!std::isfinite(qx) || !std::isfinite(qy)) fail(DGD_EINVAL, "non-finite wave vector");
+    if (std::hypot(qx, qy) * t.h > kSignalMaxQH) fail(DGD_EINVAL, "|q| h must be <= 4");
+    for (int o = 0; o < 2; ++o)
+      for (int p = 0; p < t.nq; ++p) {
+        const double* Q = t.quad_host + ((size_t)o * t.nq + p) * (3 + np);
+        const double ph = t.h * (qx * (Q[0] - 0.5) + qy * (Q[1] - 0.5));
+        const double wc = Q[2] * t.h * t.h * std::cos(ph), ws = Q[2] * t.h * t.h * std::sin(ph);
+        for (int j = 0; j < np; ++j) {
+          W[(((size_t)k * 2 + o) * np + j) * 2] += wc * Q[3 + j];
+          W[(((size_t)k * 2 + o) * np + j) * 2 + 1] += ws * Q[3 + j];
+        }
+      }
+  }
+  const Shape sh = element_shape(t.E, 64, 4, true, 0);
+  double *dW = nullptr, *dq = nullptr, *part = nullptr, *dout = nullptr;
+  int* bs = nullptr;
+  auto cleanup = [&]() {
+    (void)hipFree(dW); (void)hipFree(dq); (void)hipFree(part); (void)hipFree(dout); (void)hipFree(bs);
+  };
+  try {
+    dW = (double*)upload(W);
+    dq = (double*)upload(std::vector<double>(q, q + 2 * (size_t)nq));
+    bs = (int*)upload(std::vector<int>{0, (int)sh.blocks});
+    DGD_HIP_CHECK(hipMalloc(&part, (size_t)sh.blocks * R * nq * 2 * sizeof(double)));
+    DGD_HIP_CHECK(hipMalloc(&dout, (size_t)R * nq * 2 * sizeof(double)));
+    launch_signal(t.prec == DGD_FP64 ? 0 : 1, np, run->U, t.elem, t.E, dW, dq, nq, run->d_x0, t.h, R,
+                  sh, part, run->stream);
+    launch_reduce_width(part, bs, 1, R, nq * 2, dout, run->stream);
+    DGD_HIP_CHECK(hipGetLastError());
+    DGD_HIP_CHECK(hipMemcpyAsync(out, dout, (size_t)R * nq * 2 * sizeof(double),
+                                 hipMemcpyDeviceToHost, run->stream));
+    DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
+}
+
 void check_points(const MeshHost& mh, const double* points, int n, int offset = 0) {
   for (int r = 0; r < n; ++r) {
     const double x = points[2 * r], y = points[2 * r + 1];
@@ -860,9 +913,9 @@ int dgd_operator_build(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, dou
       op->d_W = (double*)upload(Wp);
       op->d_Mass = (double*)upload(Mp);
       if (p == 3 && precision == DGD_FP32) build_p3_tables(op);
-      std::vector<double> quad = build_ic_quadrature(R, kQuadN);
+      op->quad = build_ic_quadrature(R, kQuadN);
       op->nq = kQuadN * kQuadN;
-      op->d_quad = (double*)upload(quad);
+      op->d_quad = (double*)upload(op->quad);
       const double dt_formula = 0.1 * h * h / (D_um2_per_ms * (p + 1) * (p + 1));
       if (dt_max_ms > 0) {
         op->dt_nom = std::min(dt_formula, dt_max_ms);
@@ -972,6 +1025,15 @@ int dgd_run_moments(dgd_run* run, double* moments_out) {
   });
 }
 
+int dgd_run_signal(dgd_run* run, const double* q, int32_t n_q, double* signal_out) {
+  return guarded([&]() -> int {
+    if (!run || !q || !signal_out) fail(DGD_EINVAL, "NULL argument");
+    if (n_q < 1) fail(DGD_EINVAL, "n_q must be >= 1");
+    run_signal(run, q, n_q, signal_out);
+    return DGD_OK;
+  });
+}
+
 int dgd_run_get_state(dgd_run* run, void* host_out) {
   return guarded([&]() -> int {
     if (!run || !host_out) fail(DGD_EINVAL, "NULL argument");
@@ -1044,6 +1106,43 @@ int dgd_eap_solve(dgd_op* op, const double* points, int32_t n_points, double sig
       }
     }
     if (status) fail(status, why);
+    return DGD_OK;
+  });
+  dgd_run_destroy(run);
+  return rc;
+}
+
+int dgd_eap_solve_signal(dgd_op* op, const double* points, int32_t n_points, double sigma0_um,
+                         const double* deltas_ms, int32_t n_deltas, const double* q, int32_t n_q,
+                         double* signal_out, double* moments_out, void* d_ws, size_t ws_bytes,
+                         void* hip_stream) {
+  dgd_run* run = nullptr;
+  std::vector<std::pair<int64_t, double>> sched;
+  int rc = guarded([&]() -> int {
+    if (!op || !deltas_ms || !q || !signal_out) fail(DGD_EINVAL, "NULL argument");
+    if (n_deltas < 1 || n_q < 1) fail(DGD_EINVAL, "bad counts");
+    sched = schedule(deltas_ms, n_deltas, op->dt_nom);
+    return DGD_OK;
+  });
+  if (rc) return rc;
+  rc = dgd_run_create(op, points, n_points, sigma0_um, d_ws, ws_bytes, hip_stream, &run);
+  if (rc) return rc;
+  rc = guarded([&]() -> int {
+    std::vector<double> mom((size_t)n_points * 6), sig((size_t)n_points * n_q * 2);
+    std::string why;
+    for (int k = 0; k < n_deltas; ++k) {
+      run_advance(run, sched[k].first, sched[k].second);
+      const int mrc = run_moments(run, mom.data(), &why);
+      if (mrc) fail(mrc, why);
+      run_signal(run, q, n_q, sig.data());
+      for (int r = 0; r < n_points; ++r) {
+        std::memcpy(&signal_out[(((size_t)r * n_deltas + k) * n_q) * 2], &sig[(size_t)r * n_q * 2],
+                    (size_t)n_q * 2 * sizeof(double));
+        if (moments_out)
+          std::memcpy(&moments_out[((size_t)r * n_deltas + k) * 6], &mom[(size_t)r * 6],
+                      6 * sizeof(double));
+      }
+    }
     return DGD_OK;
   });
   dgd_run_destroy(run);

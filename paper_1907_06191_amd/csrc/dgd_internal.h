@@ -89,6 +89,7 @@ struct dgd_op {
   double* d_W = nullptr;     // [2][6][np] FP64 physical moment weights
   double* d_Mass = nullptr;  // [2][np][np] FP64 physical mass
   double* d_quad = nullptr;  // [2][nq][np+3]: reference quadrature for the initial data
+  std::vector<double> quad;  // host copy of d_quad
   int nq = 0;
   // P3 matrix-core path (FP32 state): A operands in lane order, FP64 flux
   // coefficients and mass-row weights (see the MFMA stage kernel)
@@ -113,6 +114,7 @@ struct RunTarget {
   const double* W = nullptr;     // physical moment weights [2][6][np]
   const double* Minv = nullptr;  // reference inverse mass [2][np][np]
   const double* quad = nullptr;  // initial-data quadrature
+  const double* quad_host = nullptr;  // its host copy (owned by the op)
   int nq = 0;
   int G = 1;                     // geometries
   const int* blk_geom = nullptr; // device [nblk_red] geometry of each reduction block (G > 1)

@@ -552,19 +552,95 @@ __global__ void __launch_bounds__(256) k_moments(const T* __restrict__ u,
   }
 }
 
-// out[g][r][c] = sum of part[b][r][c] over the blocks b of geometry g.  One
+// Partial q-space signal of the propagator (one geometry): for element K
+// and right-hand side r,
+//   exp(i q.(c_K - x0_r)) * sum_j Wq[q][o][j] u_K[j][r],
+// Wq the element integrals of the nodal basis times exp(i q.(x - c_K))
+// (c_K the cell centre, h^2 included), summed over the block's elements
+// into part[b][r][q][2] = (re, im).  The phase is computed in FP64 from
+// integer cell indices.  QC wave vectors per launch slice (blockIdx.z).
+// Wq: [nq][2][NP][2]; qv: [nq][2]; x0: [R][2].
+template <typename T, int NP, int QC>
+__global__ void __launch_bounds__(256) k_signal(const T* __restrict__ u,
+                                                const int4* __restrict__ elem, int64_t E,
+                                                const double* __restrict__ Wq,
+                                                const double* __restrict__ qv, int nq,
+                                                const double* __restrict__ x0, double h, int R,
+                                                int epw, int64_t nblocks,
+                                                double* __restrict__ part) {
+  __shared__ double red[4][WAVE][2 * QC];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int r = blockIdx.y * WAVE + lane;
+  const int q0 = blockIdx.z * QC;
+  const BlockIter it = block_iter(nblocks, 1);
+  for (int64_t b = it.first; b < it.end; b += it.stride) {
+    const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
+    const int64_t e1 = e0 + epw < E ? e0 + epw : E;
+    double are[QC], aim[QC];
+#pragma unroll
+    for (int k = 0; k < QC; ++k) are[k] = aim[k] = 0.0;
+    if (r < R) {
+      const double px = x0[(int64_t)r * 2], py = x0[(int64_t)r * 2 + 1];
+      for (int64_t e = e0; e < e1; ++e) {
+        const int4 m = elem[e];
+        const int o = m.w & 1;
+        const int ci = (m.w >> 4) & 0x3fff;
+        const int cj = (m.w >> 18) & 0x3fff;
+        double uv[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) uv[j] = (double)u[(e * NP + j) * (int64_t)R + r];
+        const double dx = (ci + 0.5) * h - px;
+        const double dy = (cj + 0.5) * h - py;
+#pragma unroll
+        for (int k = 0; k < QC; ++k) {
+          const int qi = q0 + k;
+          if (qi >= nq) break;
+          const double* Wk = Wq + ((int64_t)qi * 2 + o) * NP * 2;
+          double wr = 0.0, wi = 0.0;
+#pragma unroll
+          for (int j = 0; j < NP; ++j) {
+            wr = fma(Wk[2 * j], uv[j], wr);
+            wi = fma(Wk[2 * j + 1], uv[j], wi);
+          }
+          double sn, cs;
+          sincos(qv[2 * qi] * dx + qv[2 * qi + 1] * dy, &sn, &cs);
+          are[k] += cs * wr - sn * wi;
+          aim[k] += sn * wr + cs * wi;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < QC; ++k) {
+      red[w][lane][2 * k] = are[k];
+      red[w][lane][2 * k + 1] = aim[k];
+    }
+    __syncthreads();
+    if (w == 0 && r < R) {
+      for (int k = 0; k < QC && q0 + k < nq; ++k)
+        for (int c = 0; c < 2; ++c) {
+          double sum = red[0][lane][2 * k + c];
+          for (int v = 1; v < (int)(blockDim.x / WAVE); ++v) sum += red[v][lane][2 * k + c];
+          part[((b * R + r) * (int64_t)nq + q0 + k) * 2 + c] = sum;
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// out[g][r][c] = sum of part[b][r][c] (c < W) over the blocks b of geometry g.  One
 // 64-lane workgroup per output value: each lane sums a strided subset of the
 // blocks in order, then a fixed-order tree over the 64 lanes.
 __global__ void __launch_bounds__(64) k_reduce_seg(const double* __restrict__ part,
                                                    const int* __restrict__ blk_start, int G, int R,
-                                                   double* __restrict__ out) {
-  const int t = blockIdx.x;            // (g * R + r) * 6 + c
-  if (t >= G * R * 6) return;
-  const int g = t / (R * 6);
-  const int rc = t % (R * 6);
+                                                   int W, double* __restrict__ out) {
+  const int t = blockIdx.x;            // (g * R + r) * W + c
+  if (t >= G * R * W) return;
+  const int g = t / (R * W);
+  const int rc = t % (R * W);
   const int b0 = blk_start[g], b1 = blk_start[g + 1];
   double s = 0;
-  for (int b = b0 + (int)threadIdx.x; b < b1; b += 64) s += part[(int64_t)b * R * 6 + rc];
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += 64) s += part[(int64_t)b * R * W + rc];
   __shared__ double sh[64];
   sh[threadIdx.x] = s;
   __syncthreads();
@@ -870,7 +946,28 @@ void launch_moments(int prec, int np, const void* u, const int4* elem, int64_t E
 
 void launch_reduce(const double* part, const int* blk_start, int G, int R, double* out,
                    hipStream_t st) {
-  k_reduce_seg<<<dim3((unsigned)(G * R * 6)), dim3(64), 0, st>>>(part, blk_start, G, R, out);
+  k_reduce_seg<<<dim3((unsigned)(G * R * 6)), dim3(64), 0, st>>>(part, blk_start, G, R, 6, out);
+}
+
+void launch_signal(int prec, int np, const void* u, const int4* elem, int64_t E, const double* Wq,
+                   const double* qv, int nq, const double* x0, double h, int R, const Shape& sh,
+                   double* part, hipStream_t st) {
+  constexpr int QC = 8;
+  const dim3 grid((unsigned)sh.grid, (unsigned)((R + WAVE - 1) / WAVE), (unsigned)((nq + QC - 1) / QC));
+  if (prec == 0) {
+    DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_signal<double, NP, QC>), grid, dim3(64 * sh.waves), 0,
+                                           st, (const double*)u, elem, E, Wq, qv, nq, x0, h, R,
+                                           sh.epw, sh.blocks, part));
+  } else {
+    DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_signal<float, NP, QC>), grid, dim3(64 * sh.waves), 0,
+                                           st, (const float*)u, elem, E, Wq, qv, nq, x0, h, R,
+                                           sh.epw, sh.blocks, part));
+  }
+}
+
+void launch_reduce_width(const double* part, const int* blk_start, int G, int R, int W,
+                         double* out, hipStream_t st) {
+  k_reduce_seg<<<dim3((unsigned)(G * R * W)), dim3(64), 0, st>>>(part, blk_start, G, R, W, out);
 }
 
 void launch_ic_mass(int np, const int4* elem, int64_t E, const double* quad, int nq,

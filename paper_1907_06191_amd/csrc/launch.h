@@ -64,6 +64,16 @@ void launch_moments(int prec, int np, const void* u, const int4* elem, int64_t E
 void launch_reduce(const double* part, const int* blk_start, int G, int R, double* out,
                    hipStream_t st);
 
+// Partial q-space signal per block: part[b][r][q][2] = (re, im) of the
+// block's elements' sum of exp(i q.(c_K - x0_r)) sum_j Wq[q][o][j] u_K[j][r]
+// (one geometry; Wq [nq][2][np][2], qv [nq][2], x0 [R][2]).
+void launch_signal(int prec, int np, const void* u, const int4* elem, int64_t E, const double* Wq,
+                   const double* qv, int nq, const double* x0, double h, int R, const Shape& sh,
+                   double* part, hipStream_t st);
+// launch_reduce over W values per (geometry, right-hand side).
+void launch_reduce_width(const double* part, const int* blk_start, int G, int R, int W,
+                         double* out, hipStream_t st);
+
 // Initial data.  The mass pass writes part[b][r][0] = sum of h^2 w_q g(x_q)
 // over the block's elements; the project pass writes
 // u = M^-1 (sum_q w_q g phi) / mass[g][r].

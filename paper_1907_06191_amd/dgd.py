@@ -104,6 +104,9 @@ _sig("dgd_eap_solve_expm", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, 
 _sig("dgd_eap_solve", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, ctypes.c_int32, _c_dp,
                        _c_dp, _vp, ctypes.c_size_t, _vp])
 _sig("dgd_autotune", [_vp, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_int32), _c_dp])
+_sig("dgd_run_signal", [_vp, _c_dp, ctypes.c_int32, _c_dp])
+_sig("dgd_eap_solve_signal", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, ctypes.c_int32, _c_dp,
+                              ctypes.c_int32, _c_dp, _c_dp, _vp, ctypes.c_size_t, _vp])
 _sig("dgd_tune_export", [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)])
 _sig("dgd_tune_import", [ctypes.c_char_p])
 _sig("dgd_tune_clear", [], None)
@@ -308,6 +311,31 @@ def dgd_eap_solve(op, points, sigma0: float, deltas, workspace=None, ws_bytes: i
     _check(_lib.dgd_eap_solve(op, _ptr(pts), n, float(sigma0), _ptr(d), int(d.size), _ptr(sig), _ptr(mom),
                               _dev_ptr(workspace), int(ws_bytes), _stream_ptr(stream)))
     return sig, mom
+
+
+def dgd_run_signal(run, q, n_points: int) -> np.ndarray:
+    """Complex signal [n_points][n_q] of the run's current state."""
+    qq = _f64(q, (2,))
+    out = np.zeros((n_points, qq.shape[0], 2))
+    _check(_lib.dgd_run_signal(run, _ptr(qq), int(qq.shape[0]), _ptr(out)))
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def dgd_eap_solve_signal(op, points, sigma0: float, deltas, q, workspace=None, ws_bytes: int = 0,
+                         stream=None):
+    """Returns (signal complex [n][nDelta][n_q], moments [n][nDelta][6])."""
+    pts = _f64(points, (2,))
+    d = _f64(deltas).ravel()
+    qq = _f64(q, (2,))
+    n = pts.shape[0]
+    sig = np.zeros((n, d.size, qq.shape[0], 2))
+    sg = np.zeros((n, d.size, 6))
+    if workspace is not None and not ws_bytes:
+        ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib.dgd_eap_solve_signal(op, _ptr(pts), n, float(sigma0), _ptr(d), int(d.size), _ptr(qq),
+                                     int(qq.shape[0]), _ptr(sig), _ptr(sg), _dev_ptr(workspace),
+                                     int(ws_bytes), _stream_ptr(stream)))
+    return sig[..., 0] + 1j * sig[..., 1], sg
 
 
 def dgd_mesh_occupancy(mesh, size: int = 64) -> np.ndarray:

@@ -53,13 +53,28 @@ def test_fullsize_rk3_fp32_first_deltas(case):
     say(f"full-size RK3 P{gold['p']} FP32: {gold['n_elements']} elements, {pts.shape[0]} points, "
         f"dt {gold['dt_nom']:.4e} ms, Delta {gold['deltas'][:nd]}")
     op = dgd.Operator(mesh, gold["p"], c["D"], c["eta"], dgd.DGD_FP32, dt_max_ms=gold["dt_nom"])
-    sig, mom = op.solve(pts, c["sigma0"], gold["deltas"][:nd])
+    # with the q-space signal at every Delta: E(0) = M0 and the small-q
+    # expansion E(eps u) = M0 + i eps u.m1 - eps^2 u^T M2 u / 2 + O(eps^3)
+    # hold against the FP64 moment kernel at any size
+    eps = 1e-3
+    dirs = np.array([[1.0, 0.0], [0.0, 1.0], [0.6, 0.8]])
+    qs = np.concatenate([np.zeros((1, 2)), eps * dirs, [[1.0, 0.5]]])
+    E, mom = dgd.dgd_eap_solve_signal(op.handle, pts, c["sigma0"], gold["deltas"][:nd], qs)
+    sig = omom.sigma_a(mom)
     ref = omom.sigma_a(np.asarray(gold["moments"])[:, :nd])
     err = omom.rel_err(sig[idx], ref)
     drift = np.abs(mom[..., 0] - 1).max()
     say(f"  max rel err vs oracle {err.max():.2e}; |M0-1| {drift:.2e}")
     assert err.max() < 1e-4
     assert drift < 1e-5
+    assert np.abs(E[..., 0] - mom[..., 0]).max() < 1e-12
+    m1 = mom[..., 1:3]
+    M2 = np.stack([np.stack([mom[..., 3], mom[..., 4]], -1), np.stack([mom[..., 4], mom[..., 5]], -1)], -2)
+    for k, u in enumerate(dirs):
+        first = eps * (m1 @ u)
+        second = 0.5 * eps ** 2 * np.einsum("...i,...ij,j->...", np.broadcast_to(u, m1.shape), M2, u)
+        assert np.abs(E[..., 1 + k].imag - first).max() < 1e-4 * np.abs(first).max()
+        assert np.abs((mom[..., 0] - E[..., 1 + k].real) - second).max() < 1e-3 * np.abs(second).max()
     op.close()
 
 
