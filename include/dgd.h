@@ -181,9 +181,15 @@ int dgd_run_moments(dgd_run* run, double* moments_out);
 int dgd_run_signal(dgd_run* run, const double* q, int32_t n_q, double* signal_out);
 
 /* Copy the state to or from the host (checkpoint / resume); host buffer of
- * n_active * np * n_points values of the op's state type.  Synchronous. */
+ * n_active * np * n_points values of the op's state type.  Synchronous.
+ * A checkpoint is the state and the step count: FP32 stores round
+ * stochastically with the step count in the salt, so a resumed run repeats
+ * the uninterrupted one bit for bit when its step count is restored too. */
 int dgd_run_get_state(dgd_run* run, void* host_out);
 int dgd_run_set_state(dgd_run* run, const void* host_in);
+/* Steps taken by the run (since creation or the last set). */
+int dgd_run_step_count(const dgd_run* run, int64_t* steps_out);
+int dgd_run_set_step_count(dgd_run* run, int64_t steps);
 
 /* The stage kernel and launch shape the run uses: kernel 0 = one element
  * and up to 64 right-hand sides per wave, 1 = several elements per wave

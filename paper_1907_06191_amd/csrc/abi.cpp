@@ -195,19 +195,20 @@ Shape pick_shape(const RunTarget& t, int R, StageKind kind) {
 }
 
 void stage(const RunTarget& t, StageKind kind, const Shape& sh, const void* us, const void* ub,
-           void* out, int mode, double cb, double cg, int R, hipStream_t st) {
+           void* out, int mode, double cb, double cg, int R, hipStream_t st,
+           const uint32_t* step = nullptr, int stage_id = 0) {
   switch (kind) {
     case kMfma:
       launch_stage_p3_mfma(us, ub, out, t.elem, t.E, t.Atab, t.Ctab, t.Wtab, t.wsum, mode, cb, cg,
-                           R, sh, st);
+                           R, sh, st, step, stage_id);
       break;
     case kPacked:
       launch_stage_packed(t.prec == DGD_FP64 ? 0 : 1, t.np, packed_group(R), us, ub, out, t.elem,
-                          t.E, t.S, t.F, t.N, mode, cb, cg, R, sh, st);
+                          t.E, t.S, t.F, t.N, mode, cb, cg, R, sh, st, step, stage_id);
       break;
     default:
       launch_stage(t.prec == DGD_FP64 ? 0 : 1, t.np, us, ub, out, t.elem, t.E, t.S, t.N, mode, cb,
-                   cg, R, sh, st);
+                   cg, R, sh, st, step, stage_id);
   }
 }
 
@@ -347,7 +348,7 @@ double power_lambda(dgd_op* op, int iters) {
 
 // ---------------------------------------------------------------- runs ----
 
-void ws_layout(const RunTarget& t, int R, size_t* total, size_t off[7]) {
+void ws_layout(const RunTarget& t, int R, size_t* total, size_t off[8]) {
   const size_t st = align256((size_t)t.E * t.np * R * state_bytes(t.prec));
   size_t o = 0;
   off[0] = o; o += st;                                            // U
@@ -357,6 +358,7 @@ void ws_layout(const RunTarget& t, int R, size_t* total, size_t off[7]) {
   off[4] = o; o += align256((size_t)t.nblk_red * R * 6 * 8);      // partials
   off[5] = o; o += align256((size_t)t.G * R * 6 * 8);             // moments
   off[6] = o; o += align256((size_t)(t.G + 1) * sizeof(int));     // block ranges
+  off[7] = o; o += 256;                                           // step counter
   *total = o;
 }
 
@@ -373,7 +375,7 @@ void run_destroy(dgd_run* run) {
 // the initial pulse of every (geometry, start point).
 dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, void* d_ws,
                     size_t ws_bytes, void* hip_stream) {
-  size_t total, off[7];
+  size_t total, off[8];
   ws_layout(t, R, &total, off);
   auto* run = new dgd_run();
   try {
@@ -403,6 +405,8 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
     run->d_part = (double*)(base + off[4]);
     run->d_mom = (double*)(base + off[5]);
     run->d_blk_start = (int*)(base + off[6]);
+    run->d_step = (uint32_t*)(base + off[7]);
+    DGD_HIP_CHECK(hipMemsetAsync(run->d_step, 0, sizeof(uint32_t), run->stream));
     if (!t.blk_start) {
       // one geometry: all reduction blocks
       const int bs[2] = {0, (int)t.nblk_red};
@@ -448,10 +452,12 @@ void run_stage_steps(dgd_run* run, int64_t n, double dt) {
     // Shu-Osher SSP-RK3 as corrections of u^n:
     //   u1 = u + dt L u;  u2 = u + 1/4 (u1 - u) + 1/4 dt L u1;  u' = u + 2/3 (u2 - u) + 2/3 dt L u2
     const StageKind k = (StageKind)run->kind;
-    stage(t, k, run->sh, run->U, nullptr, run->U1, 1, 0.0, gam, run->R, run->stream);
-    stage(t, k, run->sh, run->U1, run->U, run->U2, 1, 0.25, 0.25 * gam, run->R, run->stream);
+    stage(t, k, run->sh, run->U, nullptr, run->U1, 1, 0.0, gam, run->R, run->stream, run->d_step, 0);
+    stage(t, k, run->sh, run->U1, run->U, run->U2, 1, 0.25, 0.25 * gam, run->R, run->stream,
+          run->d_step, 1);
     stage(t, k, run->sh, run->U2, run->U, run->U, 1, 2.0 / 3.0, 2.0 / 3.0 * gam, run->R,
-          run->stream);
+          run->stream, run->d_step, 2);
+    launch_step_bump(run->d_step, run->stream);
   }
 }
 
@@ -489,6 +495,7 @@ void run_advance(dgd_run* run, int64_t n_steps, double dt) {
   run_stage_steps(run, left, dt);
   DGD_HIP_CHECK(hipGetLastError());
   run->t_ms += n_steps * dt;
+  run->steps += n_steps;
 }
 
 // FP64 moments [G][R][6]; returns DGD_EUNSTABLE (moments filled anyway) on a
@@ -671,7 +678,7 @@ size_t batch_group_bytes(const dgd_batch::Group& grp, const dgd_batch* b, RunTar
   t.E = E;
   t.G = (int)grp.geoms.size();
   t.nblk_red = E / kReducePer;
-  size_t total, off[7];
+  size_t total, off[8];
   ws_layout(t, b->R, &total, off);
   if (t_out) *t_out = t;
   return total;
@@ -957,7 +964,7 @@ int dgd_workspace_size(const dgd_op* op, int32_t n_points, size_t* bytes) {
   return guarded([&]() -> int {
     if (!op || !bytes) fail(DGD_EINVAL, "NULL argument");
     if (n_points < 1) fail(DGD_EINVAL, "n_points must be >= 1");
-    size_t off[7];
+    size_t off[8];
     ws_layout(plain_target(op), n_points, bytes, off);
     return DGD_OK;
   });
@@ -1064,6 +1071,26 @@ int dgd_run_kernel(const dgd_run* run, int32_t* kernel_out, int64_t* shape_out) 
       shape_out[2] = run->sh.remap ? 1 : 0;
       shape_out[3] = run->sh.grid;
     }
+    return DGD_OK;
+  });
+}
+
+int dgd_run_step_count(const dgd_run* run, int64_t* steps_out) {
+  return guarded([&]() -> int {
+    if (!run || !steps_out) fail(DGD_EINVAL, "NULL argument");
+    *steps_out = run->steps;
+    return DGD_OK;
+  });
+}
+
+int dgd_run_set_step_count(dgd_run* run, int64_t steps) {
+  return guarded([&]() -> int {
+    if (!run) fail(DGD_EINVAL, "run is NULL");
+    if (steps < 0) fail(DGD_EINVAL, "steps must be >= 0");
+    const uint32_t v = (uint32_t)steps;
+    DGD_HIP_CHECK(hipMemcpyAsync(run->d_step, &v, sizeof(v), hipMemcpyHostToDevice, run->stream));
+    DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+    run->steps = steps;
     return DGD_OK;
   });
 }

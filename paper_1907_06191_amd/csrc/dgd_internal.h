@@ -143,6 +143,8 @@ struct dgd_run {
   double* d_part = nullptr;   // [nblk_red][R][6] partial sums
   double* d_mom = nullptr;    // [G][R][6]
   int* d_blk_start = nullptr; // [G + 1] (plain runs: {0, nblk_red})
+  uint32_t* d_step = nullptr; // steps taken (salt of the stochastic rounding)
+  int64_t steps = 0;
   dgd::Shape sh;              // stage launch shape
   int kind = 0;               // stage kernel (VALU, packed, matrix cores)
   std::vector<double> x0;

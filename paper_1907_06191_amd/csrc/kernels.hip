@@ -87,8 +87,23 @@ __device__ __forceinline__ float round_stochastic(double v, uint32_t salt) {
   return ex - 897u <= 252u ? sr : (float)v;          // 2^-126 <= |v| < 2^127
 }
 
-__device__ __forceinline__ uint32_t state_salt(int meta, int slot) {
-  return (uint32_t)meta ^ ((uint32_t)slot * 0x85EBCA6Bu);
+// Salt of a stored value: the element's metadata and the (node,
+// right-hand side) slot, plus a mix of the run's step counter and the stage
+// within the step.  The counter makes the random threshold of a slot change
+// every step even when its value does not: with a threshold fixed per value,
+// a slot whose per-step increment stays below its threshold would never
+// move (the stagnation of rounding to nearest, for that share of slots),
+// which shows near equilibrium, where increments are a small fraction of an
+// ulp step after step.
+__device__ __forceinline__ uint32_t state_salt(int meta, int slot, uint32_t smix) {
+  return ((uint32_t)meta ^ ((uint32_t)slot * 0x85EBCA6Bu)) + smix;
+}
+
+// Per-launch part of the salt; step is the run's device step counter
+// (NULL: 0), stage_id 0..2 the stage within the RK3 step.
+__device__ __forceinline__ uint32_t step_mix(const uint32_t* step, int stage_id) {
+  const uint32_t k = step ? step[0] : 0u;
+  return (k * 3u + (uint32_t)stage_id) * 0x9E3779B9u;
 }
 __device__ __forceinline__ void store_state(float* p, int64_t i, double v, uint32_t salt) {
   p[i] = round_stochastic(v, salt);
@@ -119,7 +134,8 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
                                                const double* __restrict__ S,
                                                const double* __restrict__ Nm, int mode, double cb,
                                                double cg, int R, int epw, int64_t nblocks,
-                                               int remap, TS* res = nullptr, double ck = 0.0) {
+                                               int remap, const uint32_t* step, int stage_id,
+                                               TS* res = nullptr, double ck = 0.0) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   // right-hand sides: 64 per wave, chunk blockIdx.y; lanes past R load a
@@ -128,6 +144,7 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
   const bool live = r_raw < R;
   const int r = live ? r_raw : R - 1;
   const bool use_base = ub != nullptr;
+  const uint32_t smix = step_mix(step, stage_id);
   const BlockIter it = block_iter(nblocks, remap);
   for (int64_t b = it.first; b < it.end; b += it.stride) {
     const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
@@ -201,13 +218,13 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
         for (int i = 0; i < NP; ++i) {
           const double b0 = (double)sb[i];
           store_state(out, self + (int64_t)i * R, b0 + cb * ((double)su[i] - b0) + cg * acc[i],
-                      state_salt(m.w, i * R + r));
+                      state_salt(m.w, i * R + r, smix));
         }
       } else {
 #pragma unroll
         for (int i = 0; i < NP; ++i)
           store_state(out, self + (int64_t)i * R, (double)su[i] + cg * acc[i],
-                      state_salt(m.w, i * R + r));
+                      state_salt(m.w, i * R + r, smix));
       }
     }
   }
@@ -244,7 +261,8 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
                                                        const double* __restrict__ Wtab,
                                                        double inv_wsum, int mode, double cb,
                                                        double cg, int R, int epw, int64_t nblocks,
-                                                       int remap) {
+                                                       int remap, const uint32_t* step,
+                                                       int stage_id) {
   typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -255,6 +273,7 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
   const int c_raw = blockIdx.y * WAVE + 4 * n;
   const bool col_live = c_raw < R;
   const uint32_t col = (uint32_t)(col_live ? c_raw : 0);
+  const uint32_t smix = step_mix(step, stage_id);
   const BlockIter it = block_iter(nblocks, remap);
   for (int64_t b = it.first; b < it.end; b += it.stride) {
     const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
@@ -331,7 +350,7 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
           } else {
             const double uu = (double)u0[i][t], bb = (double)b0[i][t];
             r4[t] = round_stochastic(bb + cb * (uu - bb) + cg * val,
-                                     state_salt(m.w, row * R + (int)col + t));
+                                     state_salt(m.w, row * R + (int)col + t, smix));
           }
         }
         *(f32x4*)(out + idx) = r4;
@@ -364,7 +383,8 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
                                                       const double* __restrict__ Fm,
                                                       const double* __restrict__ Nm, int mode,
                                                       double cb, double cg, int R, int epw,
-                                                      int64_t nblocks, int remap) {
+                                                      int64_t nblocks, int remap,
+                                                      const uint32_t* step, int stage_id) {
   constexpr int RL = WAVE / G;
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -373,6 +393,7 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
   const bool live_r = r_raw < R;
   const int r = live_r ? r_raw : R - 1;
   const bool use_base = ub != nullptr;
+  const uint32_t smix = step_mix(step, stage_id);
   const BlockIter it = block_iter(nblocks, remap);
   for (int64_t b = it.first; b < it.end; b += it.stride) {
     const int64_t q0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
@@ -458,13 +479,13 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
           for (int i = 0; i < NP; ++i) {
             const double b0 = (double)sb[i];
             store_state(out, self + (int64_t)i * R, b0 + cb * ((double)su[i] - b0) + cg * acc[i],
-                        state_salt(m.w, i * R + r));
+                        state_salt(m.w, i * R + r, smix));
           }
         } else {
 #pragma unroll
           for (int i = 0; i < NP; ++i)
             store_state(out, self + (int64_t)i * R, (double)su[i] + cg * acc[i],
-                        state_salt(m.w, i * R + r));
+                        state_salt(m.w, i * R + r, smix));
         }
       };
       if (!mixed) {
@@ -844,11 +865,18 @@ __global__ void k_fill_random(T* x, int64_t n, uint64_t seed) {
 
 template <typename T, int NP>
 void stage_t(const void* us, const void* ub, void* out, const int4* elem, int64_t E, const void* S,
-             const void* N, int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st) {
+             const void* N, int mode, double cb, double cg, int R, const Shape& sh,
+             const uint32_t* step, int stage_id, hipStream_t st) {
   const unsigned chunks = (unsigned)((R + 63) / 64);
   hipLaunchKernelGGL((k_stage<T, NP>), dim3((unsigned)sh.grid, chunks), dim3(64 * sh.waves), 0, st,
                      (const T*)us, (const T*)ub, (T*)out, elem, E, (const double*)S,
-                     (const double*)N, mode, cb, cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0);
+                     (const double*)N, mode, cb, cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0, step,
+                     stage_id);
+}
+
+// Advance a run's step counter (one lane, a vector store).
+__global__ void k_step_bump(uint32_t* step) {
+  if (threadIdx.x == 0) step[0] = step[0] + 1u;
 }
 
 }  // namespace
@@ -877,23 +905,30 @@ Shape element_shape(int64_t E, int epw, int waves, bool xcd_remap, int64_t max_g
 
 void launch_stage(int prec, int np, const void* us, const void* ub, void* out, const int4* elem,
                   int64_t E, const void* S, const void* N, int mode, double cb, double cg, int R,
-                  const Shape& sh, hipStream_t st) {
+                  const Shape& sh, hipStream_t st, const uint32_t* step, int stage_id) {
   if (prec == 0) {
-    DGD_DISPATCH_NP(np, stage_t<double, NP>(us, ub, out, elem, E, S, N, mode, cb, cg, R, sh, st));
+    DGD_DISPATCH_NP(np, stage_t<double, NP>(us, ub, out, elem, E, S, N, mode, cb, cg, R, sh, step,
+                                            stage_id, st));
   } else {
-    DGD_DISPATCH_NP(np, stage_t<float, NP>(us, ub, out, elem, E, S, N, mode, cb, cg, R, sh, st));
+    DGD_DISPATCH_NP(np, stage_t<float, NP>(us, ub, out, elem, E, S, N, mode, cb, cg, R, sh, step,
+                                           stage_id, st));
   }
+}
+
+void launch_step_bump(uint32_t* step, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_bump, dim3(1), dim3(64), 0, st, step);
 }
 
 void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub, void* out,
                          const int4* elem, int64_t E, const void* S, const void* F, const void* N,
-                         int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st) {
+                         int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st,
+                         const uint32_t* step, int stage_id) {
 #define DGD_PACKED_LAUNCH(T, GG)                                                                \
   DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage_packed<T, NP, GG>), dim3((unsigned)sh.grid),  \
                                          dim3(64 * sh.waves), 0, st, (const T*)us, (const T*)ub, \
                                          (T*)out, elem, E, (const double*)S, (const double*)F,   \
                                          (const double*)N, mode, cb, cg, R, sh.epw, sh.blocks,   \
-                                         sh.remap ? 1 : 0))
+                                         sh.remap ? 1 : 0, step, stage_id))
   if (prec == 0 && G == 4) {
     DGD_PACKED_LAUNCH(double, 4);
   } else if (prec == 0) {
@@ -908,11 +943,12 @@ void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub
 
 void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4* elem, int64_t E,
                           const float* Atab, const double* Ctab, const double* Wtab, double wsum,
-                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st) {
+                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st,
+                          const uint32_t* step, int stage_id) {
   const dim3 grid((unsigned)sh.grid, (unsigned)((R + WAVE - 1) / WAVE));
   hipLaunchKernelGGL(k_stage_p3_mfma, grid, dim3(64 * sh.waves), 0, st, (const float*)us,
                      (const float*)ub, (float*)out, elem, E, Atab, Ctab, Wtab, 1.0 / wsum, mode, cb,
-                     cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0);
+                     cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0, step, stage_id);
 }
 
 void launch_cheb(int np, const double* tcur, const double* tprev, double* tnext, double* res,
@@ -922,7 +958,7 @@ void launch_cheb(int np, const double* tcur, const double* tprev, double* tnext,
   DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage<double, NP>), dim3((unsigned)sh.grid, chunks),
                                          dim3(64 * sh.waves), 0, st, tcur, tprev, tnext, elem, E,
                                          (const double*)S, (const double*)N, 2, 0.0, cg, R, sh.epw,
-                                         sh.blocks, sh.remap ? 1 : 0, res, ck));
+                                         sh.blocks, sh.remap ? 1 : 0, nullptr, 0, res, ck));
 }
 
 void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t st) {

@@ -26,9 +26,14 @@ Shape element_shape(int64_t E, int epw, int waves = 4, bool xcd_remap = true, in
 //   mode 1: out = base + cb * (us - base) + cg * L(us), base = ub (or us when ub is NULL)
 // with L(us)_K = S_{o,mask}(us_K - c) + sum_f N_{o,f}(us_f - c), c = us_K[node 0]
 // per right-hand side; S, N are FP64.  `ub` may equal `out`.
+// step (NULL: 0) is the run's device step counter and stage_id (0..2) the
+// stage within the step: both enter the salt of the stochastic rounding of
+// FP32 stores (modes 1, 2).
 void launch_stage(int prec, int np, const void* us, const void* ub, void* out, const int4* elem,
                   int64_t E, const void* S, const void* N, int mode, double cb, double cg, int R,
-                  const Shape& sh, hipStream_t st);
+                  const Shape& sh, hipStream_t st, const uint32_t* step = nullptr, int stage_id = 0);
+// step[0] += 1 (a one-lane kernel, so graph replays advance the counter).
+void launch_step_bump(uint32_t* step, hipStream_t st);
 
 // Packed stage for R <= 64 / G right-hand sides (G = 4: R <= 16, G = 2:
 // R <= 32): G elements per wave.  Same modes 0 and 1 as launch_stage; F is
@@ -36,14 +41,16 @@ void launch_stage(int prec, int np, const void* us, const void* ub, void* out, c
 // sum_{f not in mask} F_{o,f}.  The shape counts groups of G elements.
 void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub, void* out,
                          const int4* elem, int64_t E, const void* S, const void* F, const void* N,
-                         int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st);
+                         int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st,
+                         const uint32_t* step = nullptr, int stage_id = 0);
 
 // P3 stage on matrix cores (FP32 state, R % 16 == 0; each wave walks epw
 // elements for 64 right-hand sides, grid.y covers the rest), same modes and
 // coefficients as launch_stage, with a per-element FP64 mass correction.
 void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4* elem, int64_t E,
                           const float* Atab, const double* Ctab, const double* Wtab, double wsum,
-                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st);
+                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st,
+                          const uint32_t* step = nullptr, int stage_id = 0);
 
 // One step of the Chebyshev recurrence for exp(t L) (FP64 state):
 //   tnext = 2 (tcur + cg L(tcur)) - tprev,   res += ck * tnext.

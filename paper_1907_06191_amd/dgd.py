@@ -79,6 +79,8 @@ _sig("dgd_run_moments", [_vp, _c_dp])
 _sig("dgd_run_get_state", [_vp, _vp])
 _sig("dgd_run_set_state", [_vp, _vp])
 _sig("dgd_run_kernel", [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)])
+_sig("dgd_run_step_count", [_vp, ctypes.POINTER(ctypes.c_int64)])
+_sig("dgd_run_set_step_count", [_vp, ctypes.c_int64])
 _sig("dgd_run_destroy", [_vp], None)
 _sig("dgd_batch_workspace_size", [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)])
 _sig("dgd_batch_create", [_vp, ctypes.c_int32, _c_dp, ctypes.c_int32, ctypes.c_double, _vp, ctypes.c_size_t,
@@ -282,6 +284,16 @@ def dgd_run_get_state(run, n_values: int, dtype) -> np.ndarray:
 def dgd_run_set_state(run, state: np.ndarray) -> None:
     s = np.ascontiguousarray(state)
     _check(_lib.dgd_run_set_state(run, s.ctypes.data))
+
+
+def dgd_run_step_count(run) -> int:
+    n = ctypes.c_int64()
+    _check(_lib.dgd_run_step_count(run, ctypes.byref(n)))
+    return n.value
+
+
+def dgd_run_set_step_count(run, steps: int) -> None:
+    _check(_lib.dgd_run_set_step_count(run, int(steps)))
 
 
 KERNEL_NAMES = ("valu", "packed", "mfma")

@@ -65,15 +65,22 @@ def geometries(ids, workers=8, grid=GRID):
         return pool.starmap(geometry, [(g, grid) for g in ids], chunksize=1)
 
 
-def dg_targets(geos, deltas, p=1, dt_max=0.0):
-    """Batched DG solve of every geometry; returns (images [G][64][64],
-    targets [G][nDelta][3], seconds of the batched solve)."""
+def dg_targets(geos, deltas, p=1, dt_max=0.0, chunk=64, label="DG"):
+    """Batched DG solves of the geometries, `chunk` per batch; returns
+    (images [G][64][64], targets [G][nDelta][3], seconds of the solves)."""
     meshes = [dgd.Mesh(g.L, g.N, g.disks) for g, _ in geos]
     ops = [dgd.Operator(m, p, D, ETA, dgd.DGD_FP32, dt_max_ms=dt_max) for m in meshes]
     pts = np.stack([pp for _, pp in geos])
-    t0 = time.perf_counter()
-    sig, _ = dgd.dgd_eap_solve_batch(ops, pts, SIGMA0, deltas)
-    el = time.perf_counter() - t0
+    sig = []
+    el = 0.0
+    for i in range(0, len(ops), chunk):
+        t0 = time.perf_counter()
+        s, _ = dgd.dgd_eap_solve_batch(ops[i:i + chunk], pts[i:i + chunk], SIGMA0, deltas)
+        el += time.perf_counter() - t0
+        sig.append(s)
+        print(f"{label}: {min(i + chunk, len(ops))}/{len(ops)} geometries solved, {el:.0f}s",
+              flush=True)
+    sig = np.concatenate(sig)
     scale = 2.0 * D * np.asarray(deltas)[None, :, None]
     targets = sig.mean(axis=1) / scale                       # [G][nDelta][3]
     images = np.stack([dgd.dgd_mesh_occupancy(m.handle, GRID) for m in meshes])
@@ -108,8 +115,8 @@ def main():
     test = geometries(range(args.train_geoms, args.train_geoms + args.test_geoms), args.workers)
     rep["geometry_seconds"] = time.time() - t0
     print(f"geometries: {len(train)} train, {len(test)} test in {rep['geometry_seconds']:.0f}s", flush=True)
-    im_tr, tg_tr, t_tr = dg_targets(train, deltas)
-    im_te, tg_te, t_te = dg_targets(test, deltas)
+    im_tr, tg_tr, t_tr = dg_targets(train, deltas, label="DG train")
+    im_te, tg_te, t_te = dg_targets(test, deltas, label="DG test")
     rep["dg_seconds_train"] = t_tr
     rep["dg_seconds_test"] = t_te
     print(f"DG data: train {t_tr:.0f}s, test {t_te:.0f}s", flush=True)

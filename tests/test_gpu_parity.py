@@ -157,12 +157,13 @@ def test_determinism_graphs_and_checkpoint(dgd):
         dgd.dgd_set_option("graphs", 1 if graphs else 0)
         r = dgd.Run(op, pts, 0.3)
         if restore is not None:
-            dgd.dgd_run_set_state(r.handle, restore)
+            dgd.dgd_run_set_state(r.handle, restore[0])
+            dgd.dgd_run_set_step_count(r.handle, restore[1])
         outs = []
         for n in steps_list:
             r.advance(n, dt)
             outs.append(r.moments())
-        st = dgd.dgd_run_get_state(r.handle, nval, np.float32)
+        st = (dgd.dgd_run_get_state(r.handle, nval, np.float32), dgd.dgd_run_step_count(r.handle))
         r.close()
         dgd.dgd_set_option("graphs", 1)
         return outs, st
@@ -173,11 +174,12 @@ def test_determinism_graphs_and_checkpoint(dgd):
     for x, y, z in zip(a, b, c):
         assert np.array_equal(x, y)
         assert np.array_equal(x, z)
-    assert np.array_equal(sa, sb) and np.array_equal(sa, sc)
-    # checkpoint after 137 steps, resume for 64
+    assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[0], sc[0])
+    assert sa[1] == 201
+    # checkpoint (state and step count) after 137 steps, resume for 64
     _, s137 = run([100, 37])
     d, sd = run([64], restore=s137)
-    assert np.array_equal(sd, sa)
+    assert np.array_equal(sd[0], sa[0])
     assert np.array_equal(d[-1], a[-1])
 
 
