@@ -1,0 +1,81 @@
+"""GPU parity at full size for the 256 x 256, phi = 0.65, P3, 128-start-point
+workload against oracle values stored by tests/golden/make_full_golden.py
+(the oracle's Chebyshev exponential on the full mesh, 8 sampled start
+points, all 20 Delta).
+
+* Chebyshev exponential (FP64 state): every Delta to 30 ms, 1e-8 on Sigma.
+* RK3 on matrix cores (FP32 state, forced): the first Delta (about 150k
+  steps), 1e-4 on Sigma.
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import moments as omom
+from workloads import config, make_geometry, start_points
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "pack256-p3_oracle.json")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def case():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    from paper_1907_06191_amd import dgd
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    c = config(gold["workload"])
+    g = make_geometry(c["L"], c["N"], c["geom_seed"], phi=c["phi"], n_disks=c["n_disks"])
+    pts = start_points(g.disks, g.L, g.N, c["R"], np.random.default_rng(c["point_seed"]))
+    idx = np.asarray(gold["sample_index"])
+    assert g.disks.shape[0] == gold["n_disks"]
+    assert np.array_equal(pts[idx], np.asarray(gold["points"]))
+    mesh = dgd.Mesh(g.L, g.N, g.disks)
+    assert mesh.info()["n_active"] == gold["n_elements"]
+    return dgd, c, gold, mesh, pts, idx
+
+
+def test_fullsize_p3_expm_all_deltas(case):
+    dgd, c, gold, mesh, pts, idx = case
+    say(f"full-size P3 Chebyshev exponential: {gold['n_elements']} elements, "
+        f"{len(gold['deltas'])} Delta to {gold['deltas'][-1]:.0f} ms")
+    op = dgd.Operator(mesh, 3, c["D"], c["eta"], dgd.DGD_FP32, dt_max_ms=gold["dt_nom"])
+    sig, mom, napp = dgd.dgd_eap_solve_expm(op.handle, pts, c["sigma0"], gold["deltas"])
+    err = omom.rel_err(sig[idx], omom.sigma_a(np.asarray(gold["moments"])))
+    say(f"  {napp} operator applications; max rel err vs oracle {err.max():.2e}")
+    assert err.max() < 1e-8
+    op.close()
+
+
+def test_fullsize_p3_rk3_matrix_cores_first_delta(case):
+    dgd, c, gold, mesh, pts, idx = case
+    say(f"full-size P3 RK3 on matrix cores: dt {gold['dt_nom']:.4e} ms to Delta "
+        f"{gold['deltas'][0]} ms")
+    op = dgd.Operator(mesh, 3, c["D"], c["eta"], dgd.DGD_FP32, dt_max_ms=gold["dt_nom"])
+    dgd.dgd_set_option("p3_mfma", 1)
+    try:
+        run = dgd.Run(op, pts, c["sigma0"])
+        assert dgd.dgd_run_kernel(run.handle)[0] == "mfma"
+        run.close()
+        sig, mom = op.solve(pts, c["sigma0"], gold["deltas"][:1])
+    finally:
+        dgd.dgd_set_option("p3_mfma", 2)
+    err = omom.rel_err(sig[idx], omom.sigma_a(np.asarray(gold["moments"])[:, :1]))
+    drift = np.abs(mom[..., 0] - 1).max()
+    say(f"  max rel err vs oracle {err.max():.2e}; |M0-1| {drift:.2e}")
+    assert err.max() < 1e-4
+    assert drift < 1e-5
+    op.close()
