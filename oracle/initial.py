@@ -37,9 +37,34 @@ def _collapsed_rule(n):
     return r, s, w
 
 
+def project_dirac(op: Operator, x0: np.ndarray) -> np.ndarray:
+    """L2 projection of the point mass at x0 (the paper's Dirac pulse):
+    on the triangle holding x0, u = M_K^-1 psi(x0), so int u v = v(x0) for
+    every v of the space; its mass is exactly 1.  The triangle: cell
+    (floor(x/h), floor(y/h)), T0 when x0 lies on or below the cell's
+    diagonal, else T1."""
+    mesh = op.mesh
+    h = mesh.h
+    i = min(int(np.floor(x0[0] / h)), mesh.N - 1)
+    j = min(int(np.floor(x0[1] / h)), mesh.N - 1)
+    fx, fy = x0[0] / h - i, x0[1] / h - j
+    o = 0 if fx >= fy else 1
+    hit = np.flatnonzero((mesh.cell_i == i) & (mesh.cell_j == j) & (mesh.orient == o))
+    if hit.size != 1:
+        raise ValueError("the point lies in a removed cell or outside the box")
+    xi, et = fx - 0.5, fy - 0.5
+    psi = np.array([xi ** a * et ** b for (a, b) in monomials(op.p)])
+    coef = np.zeros((mesh.n_elements, op.Np))
+    coef[hit[0]] = op.Minv_blocks[o] @ psi
+    return coef.ravel()
+
+
 def project_gaussian(op: Operator, x0: np.ndarray, sigma0: float, n_quad: int = 14,
                      cutoff: float = 12.0) -> np.ndarray:
-    """Unit-mass L2 projection of the Gaussian at x0 (coefficients [ndof])."""
+    """Unit-mass L2 projection of the Gaussian at x0 (coefficients [ndof]);
+    sigma0 = 0 gives the projected point mass (project_dirac)."""
+    if sigma0 == 0:
+        return project_dirac(op, np.asarray(x0, dtype=np.float64))
     mesh = op.mesh
     h = mesh.h
     Np = op.Np

@@ -15,6 +15,11 @@ interior faces only (wall and box faces contribute nothing: zero Neumann
 data, eq. (3)).  h is the cell edge for all three face types.  The
 semi-discrete system is M du/dt = -A u.
 
+With an absorbing outer box (the paper's eq. (4), u = 0 on the square's
+edges) each box face F of an active triangle adds the same terms with the
+outside value zero (Nitsche):
+  - int_F ( D grad u . n v + D grad v . n u ) + int_F sigma_F u v.
+
 Basis: the oracle uses a modal basis, monomials xi**a * eta**b (a + b <= p)
 in the cell-centred scaled coordinates xi = (x - x_c)/h, eta = (y - y_c)/h,
 on purpose different from the nodal Lagrange basis of the paper (eq. (8))
@@ -63,6 +68,7 @@ class LocalOps:
     Khat: list        # [o] Np x Np stiffness
     Fself: list       # [o][f] Np x Np face self terms (with penalty)
     Fnbr: list        # [o][f] Np x Np face neighbour terms
+    Fdir: list        # [o][f] Np x Np terms of face f with zero outside value
     Wmom: list        # [o] 6 x Np: integral of psi_k * xi^a eta^b over the triangle
 
 
@@ -74,7 +80,7 @@ def local_ops(p: int, eta: float) -> LocalOps:
     gx = [poly.dx(b) for b in basis]
     gy = [poly.dy(b) for b in basis]
     pen = eta * p * p
-    Mhat, Khat, Fs, Fn, W = [], [], [], [], []
+    Mhat, Khat, Fs, Fn, Fd, W = [], [], [], [], [], []
     for o in (0, 1):
         v = VERTS[o]
         Mo = np.zeros((Np, Np))
@@ -88,7 +94,7 @@ def local_ops(p: int, eta: float) -> LocalOps:
         for a, (px, py) in enumerate(MOMENT_POWERS):
             for k in range(Np):
                 Wo[a, k] = poly.integrate_triangle(poly.pmul(basis[k], {(px, py): 1.0}), *v)
-        Fs_o, Fn_o = [], []
+        Fs_o, Fn_o, Fd_o = [], [], []
         for f, (p0, p1, nl, length) in enumerate(FACES[o]):
             ox, oy = FACE_OFFSETS[o][f]
             nb = [poly.shift(b, -ox, -oy) for b in basis]        # neighbour basis in my frame
@@ -98,8 +104,13 @@ def local_ops(p: int, eta: float) -> LocalOps:
             dn_nb = [poly.padd(poly.pscale(ngx[k], nl[0]), poly.pscale(ngy[k], nl[1])) for k in range(Np)]
             S = np.zeros((Np, Np))
             Nm = np.zeros((Np, Np))
+            Bd = np.zeros((Np, Np))
             for k in range(Np):
                 for l in range(Np):
+                    Bd[k, l] = (-poly.integrate_edge_param(poly.pmul(dn[l], basis[k]), p0, p1)
+                                - poly.integrate_edge_param(poly.pmul(dn[k], basis[l]), p0, p1)
+                                + pen * length
+                                * poly.integrate_edge_param(poly.pmul(basis[k], basis[l]), p0, p1))
                     # nl already carries the face length; the penalty term
                     # carries it explicitly.
                     s = (-0.5 * poly.integrate_edge_param(poly.pmul(dn[l], basis[k]), p0, p1)
@@ -112,12 +123,14 @@ def local_ops(p: int, eta: float) -> LocalOps:
                     Nm[k, l] = n
             Fs_o.append(S)
             Fn_o.append(Nm)
+            Fd_o.append(Bd)
         Mhat.append(Mo)
         Khat.append(Ko)
         Fs.append(Fs_o)
         Fn.append(Fn_o)
+        Fd.append(Fd_o)
         W.append(Wo)
-    return LocalOps(p=p, eta=eta, Mhat=Mhat, Khat=Khat, Fself=Fs, Fnbr=Fn, Wmom=W)
+    return LocalOps(p=p, eta=eta, Mhat=Mhat, Khat=Khat, Fself=Fs, Fnbr=Fn, Fdir=Fd, Wmom=W)
 
 
 @dataclasses.dataclass
@@ -131,6 +144,7 @@ class Operator:
     M: sp.csr_matrix          # block-diagonal mass, physical units
     L: sp.csr_matrix          # -M^-1 A
     Minv_blocks: list         # [o] physical M_o^-1
+    outer: str = "reflect"    # outer box: "reflect" (zero flux) or "absorb" (u = 0)
 
     @property
     def Np(self) -> int:
@@ -150,8 +164,25 @@ def _block_coo(rows_e, cols_e, block, Np):
     return r, c, v
 
 
-def assemble(mesh: Mesh, p: int, D: float, eta: float, loc: LocalOps | None = None) -> Operator:
-    """Global SIPG matrices A, M and L = -M^-1 A (eq. (7) in primal form)."""
+def box_faces(mesh: Mesh):
+    """[(o, f, elements)] of the faces on the square's edges: T0 bottom
+    (f 0, row 0) and right (f 1, column N-1); T1 top (f 0, row N-1) and left
+    (f 1, column 0).  The diagonal never lies on the box."""
+    N = mesh.N
+    T0 = mesh.orient == 0
+    T1 = ~T0
+    return [(0, 0, np.flatnonzero(T0 & (mesh.cell_j == 0))),
+            (0, 1, np.flatnonzero(T0 & (mesh.cell_i == N - 1))),
+            (1, 0, np.flatnonzero(T1 & (mesh.cell_j == N - 1))),
+            (1, 1, np.flatnonzero(T1 & (mesh.cell_i == 0)))]
+
+
+def assemble(mesh: Mesh, p: int, D: float, eta: float, loc: LocalOps | None = None,
+             outer: str = "reflect") -> Operator:
+    """Global SIPG matrices A, M and L = -M^-1 A (eq. (7) in primal form);
+    outer = "absorb" imposes u = 0 on the box (eq. (4))."""
+    if outer not in ("reflect", "absorb"):
+        raise ValueError("outer must be 'reflect' or 'absorb'")
     loc = loc or local_ops(p, eta)
     Np = (p + 1) * (p + 2) // 2
     h = mesh.h
@@ -184,6 +215,15 @@ def assemble(mesh: Mesh, p: int, D: float, eta: float, loc: LocalOps | None = No
             Ar.append(r); Ac.append(c); Av.append(v)
             r, c, v = _block_coo(sel, mesh.nbr[sel, f], -Minv[o] @ blk, Np)
             Lr.append(r); Lc.append(c); Lv.append(v)
+    if outer == "absorb":
+        for o, f, sel in box_faces(mesh):
+            if sel.size == 0:
+                continue
+            blk = D * loc.Fdir[o][f]
+            r, c, v = _block_coo(sel, sel, blk, Np)
+            Ar.append(r); Ac.append(c); Av.append(v)
+            r, c, v = _block_coo(sel, sel, -Minv[o] @ blk, Np)
+            Lr.append(r); Lc.append(c); Lv.append(v)
     n = E * Np
     cat = lambda xs: np.concatenate(xs) if xs else np.zeros(0)  # noqa: E731
     A = sp.coo_matrix((cat(Av), (cat(Ar), cat(Ac))), shape=(n, n)).tocsr()
@@ -194,4 +234,5 @@ def assemble(mesh: Mesh, p: int, D: float, eta: float, loc: LocalOps | None = No
         r, c, v = _block_coo(sel, sel, h * h * loc.Mhat[o], Np)
         Mr.append(r); Mc.append(c); Mv.append(v)
     M = sp.coo_matrix((cat(Mv), (cat(Mr), cat(Mc))), shape=(n, n)).tocsr()
-    return Operator(mesh=mesh, p=p, D=D, eta=eta, loc=loc, A=A, M=M, L=L, Minv_blocks=Minv)
+    return Operator(mesh=mesh, p=p, D=D, eta=eta, loc=loc, A=A, M=M, L=L, Minv_blocks=Minv,
+                    outer=outer)

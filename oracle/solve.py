@@ -24,9 +24,9 @@ class Problem:
     dt: dict
 
 
-def prepare(L, N, disks, p, D, eta, lam=None) -> Problem:
+def prepare(L, N, disks, p, D, eta, lam=None, outer="reflect") -> Problem:
     m = meshmod.build_mesh(L, N, disks)
-    op = sipg.assemble(m, p, D, eta)
+    op = sipg.assemble(m, p, D, eta, outer=outer)
     return Problem(op=op, dt=bounds.dt_rule(op, lam))
 
 
