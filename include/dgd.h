@@ -9,7 +9,8 @@
  * 1907.06191):
  *   - section 2.1, eq. (1)-(5): du/dt = div(k grad u) with k = D in the
  *     extracellular region and zero flux (reflecting) on the axon walls;
- *     this library also keeps zero flux on the outer box;
+ *     on the outer box either zero flux (the default) or u = 0 (eq. (4),
+ *     absorbing; dgd_operator_build_outer);
  *   - section 2.2: the substrate is a square holding non-overlapping disks;
  *   - section 3.3: the square is cut into pixels, each split by a diagonal
  *     into two triangles (here the lower-left to upper-right diagonal); a
@@ -50,6 +51,10 @@ extern "C" {
 #define DGD_FP64 0
 #define DGD_FP32 1
 #define DGD_BF16X3 2        /* reserved (BF16 hi/lo split products): rejected with EINVAL */
+
+/* Condition on the edges of the square (dgd_operator_build_outer). */
+#define DGD_OUTER_REFLECT 0 /* zero flux */
+#define DGD_OUTER_ABSORB 1  /* u = 0 outside (eq. (4)) */
 
 typedef struct dgd_mesh dgd_mesh;
 typedef struct dgd_op dgd_op;
@@ -92,8 +97,9 @@ int dgd_mesh_elements(const dgd_mesh* mesh, int32_t* cell_i, int32_t* cell_j, in
 
 /* Face neighbours on the host: for every active triangle in solver order,
  * the element across its faces 0, 1, 2 (T0: bottom, right, diagonal; T1:
- * top, left, diagonal; section 3.3 pixel split), -1 where the face carries
- * no flux.  nbr_out: int32 [n_active][3]. */
+ * top, left, diagonal; section 3.3 pixel split), -1 on a wall (a removed
+ * cell: no flux), -2 on the square's edge (no flux, or u = 0 with an
+ * absorbing operator, eq. (4)).  nbr_out: int32 [n_active][3]. */
 int dgd_mesh_faces(const dgd_mesh* mesh, int32_t* nbr_out);
 
 void dgd_mesh_destroy(dgd_mesh* mesh);
@@ -114,6 +120,21 @@ void dgd_mesh_destroy(dgd_mesh* mesh);
  */
 int dgd_operator_build(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, double eta,
                        int32_t precision, double dt_max_ms, dgd_op** out);
+
+/*
+ * As dgd_operator_build (which is outer = DGD_OUTER_REFLECT), with the
+ * condition on the square's edges chosen by `outer`:
+ *   DGD_OUTER_ABSORB: u = 0 on the edges (eq. (4), an absorbing boundary),
+ *     imposed weakly by the interior-penalty terms of a face whose outside
+ *     value is zero: -int (grad u . n) v - int (grad v . n) u + sigma int u v
+ *     on every edge face of an active cell.  Mass leaves through the edges,
+ *     so dgd_run_moments checks 0 <= M0 <= 1 (to a tolerance, see there)
+ *     instead of M0 = 1.  Stages run on the VALU kernels (no matrix-core
+ *     path).  Axon walls keep zero flux.
+ * Errors: as dgd_operator_build; EINVAL for another `outer`.
+ */
+int dgd_operator_build_outer(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, double eta,
+                             int32_t precision, double dt_max_ms, int32_t outer, dgd_op** out);
 
 /* Nominal step in ms and the eigenvalue estimate behind it (0 when the
  * caller fixed dt_max_ms).  Either pointer may be NULL. */
@@ -148,8 +169,13 @@ void dgd_operator_destroy(dgd_op* op);
  * dgd_run_create projects the pulse exp(-|x - x0|^2 / (2 sigma0^2)),
  * restricted to the active triangles, onto the space (L2 projection with
  * an FP64 quadrature) and scales each column to unit mass.
+ * sigma0 = 0 gives the projected point mass (the Dirac pulse of section
+ * 2.1): on the triangle holding x0 (the T0 of its cell when x0 lies on or
+ * below the cell's diagonal, else T1), u = M_K^-1 phi(x0), so that
+ * int u v = v(x0) for every v of the space; zero elsewhere; mass 1.
  *   points: host float64 [n_points][2]; each must lie in an active cell
  *           (else ENOTFREE).
+ *   sigma0_um: >= 0 and finite (else EINVAL).
  *   d_ws: NULL (the library allocates) or a device buffer of ws_bytes >=
  *         dgd_workspace_size bytes that outlives the run (else ENOMEM).
  *   hip_stream: stream every kernel of the run is launched on; NULL gives
@@ -165,8 +191,10 @@ int dgd_run_advance(dgd_run* run, int64_t n_steps, double dt_ms);
 /* FP64 moments about each start point, host [n_points][6] =
  * (M0, mx, my, Mxx, Mxy, Myy).  Synchronises the run's stream.
  * Returns EUNSTABLE if a moment is not finite or |M0 - 1| > the
- * precision's tolerance (1e-9 FP64, 1e-3 otherwise); moments_out is
- * filled either way. */
+ * precision's tolerance (1e-9 FP64, 1e-3 otherwise; with an absorbing box
+ * M0 outside [-tol, 1 + tol], tol 1e-6 FP64, 1e-3 otherwise, since the
+ * discrete solution's mass may exceed 1 by a discretisation error there);
+ * moments_out is filled either way. */
 int dgd_run_moments(dgd_run* run, double* moments_out);
 
 /* Narrow-pulse q-space signal of the propagator of each start point (the

@@ -29,7 +29,7 @@ void clear_error();
   } while (0)
 
 // Element metadata packed for one 16-byte load per element:
-//   x, y, z = neighbour element across faces 0, 1, 2 (-1: no flux),
+//   x, y, z = neighbour element across faces 0, 1, 2 (-1: wall, -2: box edge),
 //   w = orientation | face mask << 1 | cell_i << 4 | cell_j << 18.
 struct MeshHost {
   double L = 0, h = 0;
@@ -52,6 +52,8 @@ struct RefElem {
   std::vector<double> Nb;           // [2][3][np][np]  -M^-1 Fnbr_f
   std::vector<double> Fs;           // [2][3][np][np]  -M^-1 Fself_f: S_{o,7} - S_{o,mask} =
                                     //   sum over faces f not in mask of Fs_{o,f}
+  std::vector<double> Bd;           // [2][3][np][np]  -M^-1 Fdir_f: face f on the absorbing box
+                                    //   (u = 0 outside, Nitsche terms)
   std::vector<double> Mass;         // [2][np][np]
   std::vector<double> Minv;         // [2][np][np]
   std::vector<double> W;            // [2][6][np] int phi_j xi^a eta^b over the triangle,
@@ -59,6 +61,9 @@ struct RefElem {
 };
 
 RefElem build_ref_elem(int p, double eta);
+// Nodal basis values at a cell-local point (units of h, origin at the
+// cell's lower-left corner) of the orientation-o triangle.
+void eval_nodal_basis(const RefElem& R, int o, double x, double y, double* out);
 std::vector<double> build_ic_quadrature(const RefElem& R, int n);
 // Element order: cells ranked in vertical strips of `strip` columns (each
 // strip row by row; strip <= 0: plain rows); the ranked cells are taken in
@@ -85,6 +90,8 @@ struct dgd_op {
   void* d_S = nullptr;    // [2][8][np][np] FP64
   void* d_N = nullptr;    // [2][3][np][np] FP64
   void* d_F = nullptr;    // [2][3][np][np] FP64 self-face blocks (packed stage kernel)
+  int outer = DGD_OUTER_REFLECT;
+  void* d_B = nullptr;    // [2][3][np][np] FP64 absorbing-box face blocks (DGD_OUTER_ABSORB)
   double* d_Minv = nullptr;  // [2][np][np] FP64
   double* d_W = nullptr;     // [2][6][np] FP64 physical moment weights
   double* d_Mass = nullptr;  // [2][np][np] FP64 physical mass
@@ -110,6 +117,7 @@ struct RunTarget {
   const void* S = nullptr;       // FP64 [2][8][np][np]
   const void* N = nullptr;       // FP64 [2][3][np][np]
   const void* F = nullptr;       // FP64 [2][3][np][np] self-face blocks
+  const void* B = nullptr;       // FP64 [2][3][np][np] absorbing-box face blocks (NULL: zero flux)
   double D = 0, h = 0;
   const double* W = nullptr;     // physical moment weights [2][6][np]
   const double* Minv = nullptr;  // reference inverse mass [2][np][np]
@@ -124,6 +132,9 @@ struct RunTarget {
   const double* Ctab = nullptr;
   const double* Wtab = nullptr;
   double wsum = 0;
+  const RefElem* ref = nullptr;  // reference element (host)
+  // host mesh of each geometry and the row of its first element in the table
+  std::vector<std::pair<const MeshHost*, int64_t>> hosts;
 };
 
 }  // namespace dgd

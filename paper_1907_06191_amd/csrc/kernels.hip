@@ -135,7 +135,8 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
                                                const double* __restrict__ Nm, int mode, double cb,
                                                double cg, int R, int epw, int64_t nblocks,
                                                int remap, const uint32_t* step, int stage_id,
-                                               TS* res = nullptr, double ck = 0.0) {
+                                               const double* __restrict__ Bm, TS* res = nullptr,
+                                               double ck = 0.0) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   // right-hand sides: 64 per wave, chunk blockIdx.y; lanes past R load a
@@ -202,6 +203,22 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
       DGD_FACE(1, s1)
       DGD_FACE(2, s2)
 #undef DGD_FACE
+      // faces on the absorbing box (neighbour code -2; faces 0 and 1 only):
+      // the outside value is zero, so the term acts on u itself
+      if (Bm != nullptr && (m.x == -2 || m.y == -2)) {
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          if ((f == 0 ? m.x : m.y) != -2) continue;
+          const double* Bf = Bm + (o * 3 + f) * NP * NP;
+#pragma unroll
+          for (int i = 0; i < NP; ++i) {
+            double a = acc[i];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) a = fma(Bf[i * NP + j], (double)su[j], a);
+            acc[i] = a;
+          }
+        }
+      }
       if (!live) continue;
       if (mode == 0) {
 #pragma unroll
@@ -384,7 +401,8 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
                                                       const double* __restrict__ Nm, int mode,
                                                       double cb, double cg, int R, int epw,
                                                       int64_t nblocks, int remap,
-                                                      const uint32_t* step, int stage_id) {
+                                                      const uint32_t* step, int stage_id,
+                                                      const double* __restrict__ Bm) {
   constexpr int RL = WAVE / G;
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -411,6 +429,8 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
       const int o0 = __builtin_amdgcn_readfirstlane(o);
       const bool mixed = __ballot(o != o0) != 0;
       const bool partial = __ballot(mask != 7) != 0;
+      const bool box0 = Bm != nullptr && m.x == -2, box1 = Bm != nullptr && m.y == -2;
+      const bool any_box = __ballot(box0 || box1) != 0;
       // one element and right-hand side per lane with orientation oo (uniform)
       auto body = [&](const int oo) {
         const int64_t self = (e * NP) * (int64_t)R + r;
@@ -470,6 +490,24 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
         DGD_PFACE(1, s1)
         DGD_PFACE(2, s2)
 #undef DGD_PFACE
+        // absorbing box faces: lanes without one multiply exact zeros
+        if (any_box) {
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            const bool on = f == 0 ? box0 : box1;
+            const double* Bf = Bm + (oo * 3 + f) * NP * NP;
+            double ub_[NP];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) ub_[j] = on ? (double)su[j] : 0.0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+              double a = acc[i];
+#pragma unroll
+              for (int j = 0; j < NP; ++j) a = fma(Bf[i * NP + j], ub_[j], a);
+              acc[i] = a;
+            }
+          }
+        }
         if (!live) return;
         if (mode == 0) {
 #pragma unroll
@@ -866,15 +904,29 @@ __global__ void k_fill_random(T* x, int64_t n, uint64_t seed) {
 template <typename T, int NP>
 void stage_t(const void* us, const void* ub, void* out, const int4* elem, int64_t E, const void* S,
              const void* N, int mode, double cb, double cg, int R, const Shape& sh,
-             const uint32_t* step, int stage_id, hipStream_t st) {
+             const uint32_t* step, int stage_id, const void* B, hipStream_t st) {
   const unsigned chunks = (unsigned)((R + 63) / 64);
   hipLaunchKernelGGL((k_stage<T, NP>), dim3((unsigned)sh.grid, chunks), dim3(64 * sh.waves), 0, st,
                      (const T*)us, (const T*)ub, (T*)out, elem, E, (const double*)S,
                      (const double*)N, mode, cb, cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0, step,
-                     stage_id);
+                     stage_id, (const double*)B);
 }
 
 // Advance a run's step counter (one lane, a vector store).
+// Projected point masses: thread k * np + i writes coefficient i of the
+// (geometry, start point) k into its element; the state is zero elsewhere.
+// pe[k] is the element (row of the concatenated table), col[k] the column.
+template <typename T>
+__global__ void k_ic_point(const int64_t* __restrict__ pe, const int* __restrict__ col,
+                           const double* __restrict__ vals, int n, int np, int R,
+                           T* __restrict__ u) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * np) return;
+  const int64_t k = t / np;
+  const int i = (int)(t - k * np);
+  u[(pe[k] * np + i) * (int64_t)R + col[k]] = (T)vals[t];
+}
+
 __global__ void k_step_bump(uint32_t* step) {
   if (threadIdx.x == 0) step[0] = step[0] + 1u;
 }
@@ -905,13 +957,14 @@ Shape element_shape(int64_t E, int epw, int waves, bool xcd_remap, int64_t max_g
 
 void launch_stage(int prec, int np, const void* us, const void* ub, void* out, const int4* elem,
                   int64_t E, const void* S, const void* N, int mode, double cb, double cg, int R,
-                  const Shape& sh, hipStream_t st, const uint32_t* step, int stage_id) {
+                  const Shape& sh, hipStream_t st, const uint32_t* step, int stage_id,
+                  const void* B) {
   if (prec == 0) {
     DGD_DISPATCH_NP(np, stage_t<double, NP>(us, ub, out, elem, E, S, N, mode, cb, cg, R, sh, step,
-                                            stage_id, st));
+                                            stage_id, B, st));
   } else {
     DGD_DISPATCH_NP(np, stage_t<float, NP>(us, ub, out, elem, E, S, N, mode, cb, cg, R, sh, step,
-                                           stage_id, st));
+                                           stage_id, B, st));
   }
 }
 
@@ -919,16 +972,28 @@ void launch_step_bump(uint32_t* step, hipStream_t st) {
   hipLaunchKernelGGL(k_step_bump, dim3(1), dim3(64), 0, st, step);
 }
 
+void launch_ic_point(int prec, const int64_t* pe, const int* col, const double* vals, int n, int np,
+                     int R, void* u, hipStream_t st) {
+  const int64_t threads = (int64_t)n * np;
+  const unsigned grid = (unsigned)((threads + 255) / 256);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_ic_point<double>, dim3(grid), dim3(256), 0, st, pe, col, vals, n, np, R,
+                       (double*)u);
+  else
+    hipLaunchKernelGGL(k_ic_point<float>, dim3(grid), dim3(256), 0, st, pe, col, vals, n, np, R,
+                       (float*)u);
+}
+
 void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub, void* out,
                          const int4* elem, int64_t E, const void* S, const void* F, const void* N,
                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st,
-                         const uint32_t* step, int stage_id) {
+                         const uint32_t* step, int stage_id, const void* B) {
 #define DGD_PACKED_LAUNCH(T, GG)                                                                \
   DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage_packed<T, NP, GG>), dim3((unsigned)sh.grid),  \
                                          dim3(64 * sh.waves), 0, st, (const T*)us, (const T*)ub, \
                                          (T*)out, elem, E, (const double*)S, (const double*)F,   \
                                          (const double*)N, mode, cb, cg, R, sh.epw, sh.blocks,   \
-                                         sh.remap ? 1 : 0, step, stage_id))
+                                         sh.remap ? 1 : 0, step, stage_id, (const double*)B))
   if (prec == 0 && G == 4) {
     DGD_PACKED_LAUNCH(double, 4);
   } else if (prec == 0) {
@@ -953,12 +1018,13 @@ void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4*
 
 void launch_cheb(int np, const double* tcur, const double* tprev, double* tnext, double* res,
                  const int4* elem, int64_t E, const void* S, const void* N, double cg, double ck,
-                 int R, const Shape& sh, hipStream_t st) {
+                 int R, const Shape& sh, hipStream_t st, const void* B) {
   const unsigned chunks = (unsigned)((R + 63) / 64);
   DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage<double, NP>), dim3((unsigned)sh.grid, chunks),
                                          dim3(64 * sh.waves), 0, st, tcur, tprev, tnext, elem, E,
                                          (const double*)S, (const double*)N, 2, 0.0, cg, R, sh.epw,
-                                         sh.blocks, sh.remap ? 1 : 0, nullptr, 0, res, ck));
+                                         sh.blocks, sh.remap ? 1 : 0, nullptr, 0, (const double*)B,
+                                         res, ck));
 }
 
 void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t st) {

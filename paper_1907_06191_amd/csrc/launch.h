@@ -28,10 +28,12 @@ Shape element_shape(int64_t E, int epw, int waves = 4, bool xcd_remap = true, in
 // per right-hand side; S, N are FP64.  `ub` may equal `out`.
 // step (NULL: 0) is the run's device step counter and stage_id (0..2) the
 // stage within the step: both enter the salt of the stochastic rounding of
-// FP32 stores (modes 1, 2).
+// FP32 stores (modes 1, 2).  B (NULL: zero-flux box) is FP64 [2][3][np][np],
+// the blocks of faces on an absorbing box (neighbour code -2, faces 0, 1).
 void launch_stage(int prec, int np, const void* us, const void* ub, void* out, const int4* elem,
                   int64_t E, const void* S, const void* N, int mode, double cb, double cg, int R,
-                  const Shape& sh, hipStream_t st, const uint32_t* step = nullptr, int stage_id = 0);
+                  const Shape& sh, hipStream_t st, const uint32_t* step = nullptr, int stage_id = 0,
+                  const void* B = nullptr);
 // step[0] += 1 (a one-lane kernel, so graph replays advance the counter).
 void launch_step_bump(uint32_t* step, hipStream_t st);
 
@@ -42,7 +44,7 @@ void launch_step_bump(uint32_t* step, hipStream_t st);
 void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub, void* out,
                          const int4* elem, int64_t E, const void* S, const void* F, const void* N,
                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st,
-                         const uint32_t* step = nullptr, int stage_id = 0);
+                         const uint32_t* step = nullptr, int stage_id = 0, const void* B = nullptr);
 
 // P3 stage on matrix cores (FP32 state, R % 16 == 0; each wave walks epw
 // elements for 64 right-hand sides, grid.y covers the rest), same modes and
@@ -56,7 +58,7 @@ void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4*
 //   tnext = 2 (tcur + cg L(tcur)) - tprev,   res += ck * tnext.
 void launch_cheb(int np, const double* tcur, const double* tprev, double* tnext, double* res,
                  const int4* elem, int64_t E, const void* S, const void* N, double cg, double ck,
-                 int R, const Shape& sh, hipStream_t st);
+                 int R, const Shape& sh, hipStream_t st, const void* B = nullptr);
 // y = a x + b y over n values (b == 0: y is only written).
 void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t st);
 
@@ -91,6 +93,11 @@ void launch_ic_project(int prec, int np, const int4* elem, int64_t E, const doub
                        const double* Minv, const double* x0, const int* blk_geom,
                        const double* mass, double sigma0, double h, double cutoff, int R,
                        const Shape& sh, void* u, hipStream_t st);
+
+// Point-mass initial data: u[(pe[k] np + i) R + col[k]] = vals[k np + i]
+// for k < n (the rest of u is cleared by the caller).
+void launch_ic_point(int prec, const int64_t* pe, const int* col, const double* vals, int n, int np,
+                     int R, void* u, hipStream_t st);
 
 // part[b][r][0] = sum over the block's elements of x_K^T Mhat y_K (FP64).
 void launch_dot_mass(int np, const double* x, const double* y, const int4* elem, int64_t E,

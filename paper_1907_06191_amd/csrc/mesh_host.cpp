@@ -91,6 +91,18 @@ void build_mesh_host(double L, int N, const double* disks, int n_disks, int stri
       }
     }
   m.n_faces = nf / 2;
+  // faces on the square's edges: -2 (no flux unless an operator absorbs
+  // there, eq. (4)); T0 bottom / right, T1 top / left
+  for (int64_t e = 0; e < E; ++e) {
+    const int i = m.ci[e], j = m.cj[e];
+    if (m.orient[e] == 0) {
+      if (j == 0) m.nbr[e * 3 + 0] = -2;
+      if (i == N - 1) m.nbr[e * 3 + 1] = -2;
+    } else {
+      if (j == N - 1) m.nbr[e * 3 + 0] = -2;
+      if (i == 0) m.nbr[e * 3 + 1] = -2;
+    }
+  }
   // connected components by breadth-first search over interior faces
   std::vector<int32_t> comp(E, -1);
   int32_t ncomp = 0;

@@ -226,6 +226,7 @@ RefElem build_ref_elem(int p, double eta) {
   R.S.assign(2 * 8 * np * np, 0);
   R.Nb.assign(2 * 3 * np * np, 0);
   R.Fs.assign(2 * 3 * np * np, 0);
+  R.Bd.assign(2 * 3 * np * np, 0);
   R.Mass.assign(2 * np * np, 0);
   R.Minv.assign(2 * np * np, 0);
   R.W.assign(2 * 6 * np, 0);
@@ -247,10 +248,11 @@ RefElem build_ref_elem(int p, double eta) {
       }
     }
     const std::vector<double> Mi = inverse(M, np);
-    std::vector<double> Fs[3], Fn[3];
+    std::vector<double> Fs[3], Fn[3], Fd[3];
     for (int f = 0; f < 3; ++f) {
       Fs[f].assign(np * np, 0);
       Fn[f].assign(np * np, 0);
+      Fd[f].assign(np * np, 0);
       const double ex = P1[o][f][0] - P0[o][f][0], ey = P1[o][f][1] - P0[o][f][1];
       const double len = std::sqrt(ex * ex + ey * ey);
       const double nx = NRM[o][f][0], ny = NRM[o][f][1];
@@ -266,6 +268,8 @@ RefElem build_ref_elem(int p, double eta) {
             const double dnj_n = wx[j] * nx + wy[j] * ny;
             Fs[f][i * np + j] += wq * (-0.5 * dnj * v[i] - 0.5 * dni * v[j] + pen * v[i] * v[j]);
             Fn[f][i * np + j] += wq * (-0.5 * dnj_n * v[i] + 0.5 * dni * w2[j] - pen * v[i] * w2[j]);
+            // face on the absorbing box: the same terms with zero outside value
+            Fd[f][i * np + j] += wq * (-dnj * v[i] - dni * v[j] + pen * v[i] * v[j]);
           }
       }
     }
@@ -284,13 +288,15 @@ RefElem build_ref_elem(int p, double eta) {
     for (int f = 0; f < 3; ++f)
       for (int i = 0; i < np; ++i)
         for (int j = 0; j < np; ++j) {
-          double acc = 0, accs = 0;
+          double acc = 0, accs = 0, accd = 0;
           for (int k = 0; k < np; ++k) {
             acc += Mi[i * np + k] * Fn[f][k * np + j];
             accs += Mi[i * np + k] * Fs[f][k * np + j];
+            accd += Mi[i * np + k] * Fd[f][k * np + j];
           }
           R.Nb[((o * 3 + f) * np + i) * np + j] = -acc;
           R.Fs[((o * 3 + f) * np + i) * np + j] = -accs;
+          R.Bd[((o * 3 + f) * np + i) * np + j] = -accd;
         }
     for (int k = 0; k < np * np; ++k) {
       R.Mass[o * np * np + k] = M[k];
@@ -298,6 +304,12 @@ RefElem build_ref_elem(int p, double eta) {
     }
   }
   return R;
+}
+
+void eval_nodal_basis(const RefElem& R, int o, double x, double y, double* out) {
+  const Basis B = make_basis(R.p);
+  std::vector<double> gx(R.np), gy(R.np);
+  B.eval_xy(o, x, y, out, gx.data(), gy.data());
 }
 
 }  // namespace dgd

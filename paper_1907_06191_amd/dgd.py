@@ -38,6 +38,8 @@ DGD_ENOTFREE = -5
 DGD_FP64 = 0
 DGD_FP32 = 1
 DGD_BF16X3 = 2
+DGD_OUTER_REFLECT = 0
+DGD_OUTER_ABSORB = 1
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
@@ -67,6 +69,9 @@ _sig("dgd_mesh_faces", [_vp, _vp])
 _sig("dgd_mesh_destroy", [_vp], None)
 _sig("dgd_operator_build", [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                             ctypes.c_double, ctypes.POINTER(_vp)])
+_sig("dgd_operator_build_outer", [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                  ctypes.POINTER(_vp)])
 _sig("dgd_operator_dt", [_vp, _c_dp, _c_dp])
 _sig("dgd_operator_info", [_vp, ctypes.POINTER(ctypes.c_int32), _c_dp, ctypes.POINTER(ctypes.c_int32)])
 _sig("dgd_workspace_size", [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)])
@@ -221,6 +226,14 @@ def dgd_operator_build(mesh, p: int, D: float, eta: float, precision: int, dt_ma
     out = _vp()
     _check(_lib.dgd_operator_build(mesh, int(p), float(D), float(eta), int(precision), float(dt_max_ms),
                                    ctypes.byref(out)))
+    return out.value
+
+
+def dgd_operator_build_outer(mesh, p: int, D: float, eta: float, precision: int,
+                             dt_max_ms: float = 0.0, outer: int = DGD_OUTER_REFLECT) -> int:
+    out = _vp()
+    _check(_lib.dgd_operator_build_outer(mesh, int(p), float(D), float(eta), int(precision),
+                                         float(dt_max_ms), int(outer), ctypes.byref(out)))
     return out.value
 
 
@@ -521,10 +534,11 @@ class Mesh:
 
 
 class Operator:
-    def __init__(self, mesh: Mesh, p, D, eta, precision, dt_max_ms=0.0):
+    def __init__(self, mesh: Mesh, p, D, eta, precision, dt_max_ms=0.0, outer=DGD_OUTER_REFLECT):
         self._destroy = _lib.dgd_operator_destroy
         self.mesh = mesh              # keeps the mesh alive
-        self.handle = dgd_operator_build(mesh.handle, p, D, eta, precision, dt_max_ms)
+        self.outer = outer
+        self.handle = dgd_operator_build_outer(mesh.handle, p, D, eta, precision, dt_max_ms, outer)
 
     @property
     def dt(self):

@@ -78,7 +78,13 @@ def test_host_mesh_matches_oracle_mesh(name, strip, group):
     inv[perm] = np.arange(perm.size)
     onb = o.nbr[perm]
     expect = np.where(onb >= 0, inv[np.maximum(onb, 0)], -1)
-    assert np.array_equal(nbr, expect)
+    assert np.array_equal(np.where(nbr == -2, -1, nbr), expect)
+    # box-edge faces (-2) are exactly the oracle's box faces
+    from oracle import sipg
+    box = np.zeros((ci.size, 3), dtype=bool)
+    for t, f, sel in sipg.box_faces(o):
+        box[inv[sel], f] = True
+    assert np.array_equal(nbr == -2, box)
     # same set of (cell, orientation), each once
     key = lambda i, j, t: (np.asarray(j, np.int64) * g.N + np.asarray(i)) * 2 + np.asarray(t)  # noqa: E731
     assert np.array_equal(np.sort(key(ci, cj, ori)), np.sort(key(o.cell_i, o.cell_j, o.orient)))
