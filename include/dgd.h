@@ -136,6 +136,32 @@ int dgd_operator_build(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, dou
 int dgd_operator_build_outer(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, double eta,
                              int32_t precision, double dt_max_ms, int32_t outer, dgd_op** out);
 
+/*
+ * The paper's own formulation (eq. (6)-(7) with the fluxes of section
+ * 3.2) on all pixels: q = grad u with the central flux (u- + u+)/2 for u,
+ * u_t = div(k q) with the harmonic-mean flux 2 k- k+ / (k- + k+) (q- + q+)/2
+ * . n for q, k = D in extracellular cells and k = 0 in axon cells, which
+ * stay in the mesh (null work there: u keeps its initial value, zero).
+ *   mesh: normally built with no disks (every pixel active); cells it has
+ *     removed act as zero-flux walls whose u-flux is the inside value.
+ *   disks: host float64 [n_disks][3] (cx, cy, r); a cell is an axon cell
+ *     when its centroid lies strictly inside a disk (the removal test of
+ *     dgd_mesh_create).  The square's edges: zero flux, u-flux the inside
+ *     value.
+ *   p, D, precision, dt_max_ms: as dgd_operator_build (no penalty; the
+ *     power iteration runs on this operator, whose spectral radius is 4x
+ *     (P1) to 14x (P3) smaller than that of the primal form at eta = 10).
+ * Each RK stage runs two kernels: the gradient pass (q into the run's
+ * workspace, 2 np values per element and start point) and the divergence
+ * pass with the stage combine.  Start points must lie in extracellular
+ * cells (ENOTFREE).  Runs, dgd_eap_solve, the signal and operator apply
+ * take this operator; the exponential and batches reject it (EINVAL).
+ * Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+int dgd_operator_build_mixed(const dgd_mesh* mesh, const double* disks, int32_t n_disks, int32_t p,
+                             double D_um2_per_ms, int32_t precision, double dt_max_ms,
+                             dgd_op** out);
+
 /* Nominal step in ms and the eigenvalue estimate behind it (0 when the
  * caller fixed dt_max_ms).  Either pointer may be NULL. */
 int dgd_operator_dt(const dgd_op* op, double* dt_nom_ms, double* lambda_max_per_ms);

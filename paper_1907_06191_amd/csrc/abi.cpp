@@ -139,12 +139,19 @@ RunTarget plain_target(const dgd_op* op) {
   t.wsum = op->wsum;
   t.ref = &op->ref;
   t.hosts = {{&op->mesh->host, 0}};
+  t.form = op->form;
+  t.MG = op->d_MG;
+  t.MD = op->d_MD;
+  t.MN = op->d_MN;
+  t.meta = op->d_meta;
+  t.elem_ic = op->d_elem_ic;
+  t.axon_host = op->axon_cell.empty() ? nullptr : op->axon_cell.data();
   return t;
 }
 
 // Whether the P3 matrix-core kernel can run a stage on (t, R).
 bool mfma_possible(const RunTarget& t, int R) {
-  return t.Atab && !t.B && t.prec == DGD_FP32 && t.np == 10 && R % 16 == 0 &&
+  return t.Atab && !t.B && t.form == 0 && t.prec == DGD_FP32 && t.np == 10 && R % 16 == 0 &&
          (double)t.E * 10.0 * (double)R < 2147483647.0;
 }
 
@@ -156,7 +163,7 @@ const char* const kKindName[3] = {"valu", "packed", "mfma"};
 
 // The VALU kernel for (t, R): packed when R <= 32.
 StageKind valu_kind(const RunTarget& t, int R) {
-  return g_opt.packed && t.F && R <= 32 ? kPacked : kValu;
+  return g_opt.packed && t.F && t.form == 0 && R <= 32 ? kPacked : kValu;
 }
 
 int packed_group(int R) { return R <= 16 ? 4 : 2; }
@@ -191,7 +198,7 @@ StageKind stage_kind(const RunTarget& t, int R) {
 // options.
 Shape pick_shape(const RunTarget& t, int R, StageKind kind) {
   const int64_t units = stage_units(t, R, kind);
-  if (g_opt.autotune) {
+  if (g_opt.autotune && t.form == 0) {
     TuneParams p;
     if (tune_find(kind_key(t, R, kind), &p)) return tune_shape(p, units);
   }
@@ -201,6 +208,12 @@ Shape pick_shape(const RunTarget& t, int R, StageKind kind) {
 void stage(const RunTarget& t, StageKind kind, const Shape& sh, const void* us, const void* ub,
            void* out, int mode, double cb, double cg, int R, hipStream_t st,
            const uint32_t* step = nullptr, int stage_id = 0) {
+  if (t.form == 1) {
+    if (!t.qbuf) fail(DGD_EINVAL, "internal: mixed-form stage without its q buffer");
+    launch_mixed_stage(t.prec == DGD_FP64 ? 0 : 1, t.np, us, ub, out, t.qbuf, t.elem, t.meta, t.E,
+                       t.MG, t.MD, t.MN, mode, cb, cg, R, sh, st, step, stage_id);
+    return;
+  }
   switch (kind) {
     case kMfma:
       launch_stage_p3_mfma(us, ub, out, t.elem, t.E, t.Atab, t.Ctab, t.Wtab, t.wsum, mode, cb, cg,
@@ -241,6 +254,40 @@ StageKind tune_target(const RunTarget& t, int R, void* a, void* b, const void* b
     if (force || !tune_find(kind_key(t, R, k), &p)) tune_kind(t, R, k, a, b, base, st);
   }
   return stage_kind(t, R);
+}
+
+// Mixed form on the op's mesh: axon cells are the cells whose centroid lies
+// strictly inside a disk (the test that removes cells); per element the
+// face mask of the q-flux (both sides extracellular) and the extracellular
+// flag; the element table of the initial data with axon elements as
+// padding; the pass matrices.
+void build_mixed_tables(dgd_op* op, const double* disks, int n_disks) {
+  const MeshHost& mh = op->mesh->host;
+  MeshHost tmp;
+  build_mesh_host(mh.L, mh.N, disks, n_disks, 0, 1, tmp);
+  op->axon_cell.resize(tmp.active_cell.size());
+  for (size_t k = 0; k < tmp.active_cell.size(); ++k) op->axon_cell[k] = tmp.active_cell[k] ? 0 : 1;
+  const int64_t E = mh.n_elements();
+  auto axon = [&](int64_t e) { return op->axon_cell[(size_t)mh.cj[e] * mh.N + mh.ci[e]] != 0; };
+  std::vector<uint8_t> meta(E);
+  std::vector<int4> eic = op->mesh->packed;
+  for (int64_t e = 0; e < E; ++e) {
+    const bool ext = !axon(e);
+    int fm = 0;
+    if (ext)
+      for (int f = 0; f < 3; ++f) {
+        const int32_t nb = mh.nbr[(size_t)e * 3 + f];
+        if (nb >= 0 && !axon(nb)) fm |= 1 << f;
+      }
+    meta[e] = (uint8_t)(fm | (ext ? 8 : 0));
+    if (!ext) eic[e].w = (int)((uint32_t)(eic[e].w & 1) | ((uint32_t)kPadCell << 4) | ((uint32_t)kPadCell << 18));
+  }
+  op->d_meta = (uint8_t*)upload(meta);
+  op->d_elem_ic = (int4*)upload(eic);
+  op->d_MG = upload(op->ref.MG);
+  op->d_MD = upload(op->ref.MD);
+  op->d_MN = upload(op->ref.MN);
+  op->form = 1;
 }
 
 // Tables of the P3 matrix-core kernel: for class (o, mask) the stacked
@@ -310,16 +357,51 @@ double power_lambda(dgd_op* op, int iters) {
             for (int j = 0; j < np; ++j) s += std::fabs(op->ref.Bd[((o * 3 + f) * np + i) * np + j]);
         g = std::max(g, s);
       }
+  if (op->form == 1) {
+    // row-sum bounds of the two passes, multiplied
+    const RefElem& Rf = op->ref;
+    double gg = 0, gd = 0;
+    for (int o = 0; o < 2; ++o)
+      for (int mask = 0; mask < 8; ++mask)
+        for (int i = 0; i < np; ++i) {
+          double sg = 0, sd = 0;
+          for (int c = 0; c < 2; ++c) {
+            for (int j = 0; j < np; ++j) {
+              sg += std::fabs(Rf.MG[((((size_t)o * 8 + mask) * 2 + c) * np + i) * np + j]);
+              sd += std::fabs(Rf.MD[((((size_t)o * 8 + mask) * 2 + c) * np + i) * np + j]);
+            }
+            for (int f = 0; f < 3; ++f)
+              for (int j = 0; j < np; ++j) {
+                const double v = std::fabs(Rf.MN[((((size_t)o * 3 + f) * 2 + c) * np + i) * np + j]);
+                sg += v;
+                sd += v;
+              }
+          }
+          gg = std::max(gg, sg);
+          gd = std::max(gd, sd);
+        }
+    g = gg * gd;
+  }
   double* Mass = (double*)upload(op->ref.Mass);
-  double *x = nullptr, *y = nullptr, *part = nullptr, *red = nullptr;
+  double *x = nullptr, *y = nullptr, *part = nullptr, *red = nullptr, *q = nullptr;
   int* bs = nullptr;
   const Shape sh = stage_shape(E);
   const Shape shr = reduce_shape(E);
   auto cleanup = [&]() {
     (void)hipFree(Mass); (void)hipFree(x); (void)hipFree(y); (void)hipFree(part);
-    (void)hipFree(red); (void)hipFree(bs);
+    (void)hipFree(red); (void)hipFree(bs); (void)hipFree(q);
+  };
+  // y = cg L x in FP64 (the stage kernel's mode 0)
+  auto apply = [&](const double* in, double* out, double cg, hipStream_t st) {
+    if (op->form == 1)
+      launch_mixed_stage(DGD_FP64, np, in, nullptr, out, q, mesh->d_elem, op->d_meta, E, op->d_MG,
+                         op->d_MD, op->d_MN, 0, 0.0, cg, R, sh, st);
+    else
+      launch_stage(DGD_FP64, np, in, nullptr, out, mesh->d_elem, E, op->d_S, op->d_N, 0, 0.0, cg, R,
+                   sh, st, nullptr, 0, op->d_B);
   };
   try {
+    if (op->form == 1) DGD_HIP_CHECK(hipMalloc(&q, 2 * n * sizeof(double)));
     DGD_HIP_CHECK(hipMalloc(&x, n * sizeof(double)));
     DGD_HIP_CHECK(hipMalloc(&y, n * sizeof(double)));
     DGD_HIP_CHECK(hipMalloc(&part, shr.blocks * R * 6 * sizeof(double)));
@@ -330,8 +412,7 @@ double power_lambda(dgd_op* op, int iters) {
     const int4* elem = mesh->d_elem;
     std::vector<double> nrm(R * 6);
     for (int it = 0; it < iters; ++it) {
-      launch_stage(DGD_FP64, np, x, nullptr, y, elem, E, op->d_S, op->d_N, 0, 0.0, 1.0 / g, R, sh, st,
-                   nullptr, 0, op->d_B);
+      apply(x, y, 1.0 / g, st);
       std::swap(x, y);
       // each step shrinks x by about lambda / g: rescale every 16 steps by
       // the largest column norm so that nothing underflows
@@ -348,8 +429,7 @@ double power_lambda(dgd_op* op, int iters) {
     }
     DGD_HIP_CHECK(hipGetLastError());
     // y = L x (unscaled); lambda = -(x, M y) / (x, M x)
-    launch_stage(DGD_FP64, np, x, nullptr, y, elem, E, op->d_S, op->d_N, 0, 0.0, 1.0, R, sh, st,
-                 nullptr, 0, op->d_B);
+    apply(x, y, 1.0, st);
     std::vector<double> xmy(R * 6), xmx(R * 6);
     launch_dot_mass(np, x, y, elem, E, Mass, R, shr, part, st);
     launch_reduce(part, bs, 1, R, red, st);
@@ -370,7 +450,7 @@ double power_lambda(dgd_op* op, int iters) {
 
 // ---------------------------------------------------------------- runs ----
 
-void ws_layout(const RunTarget& t, int R, size_t* total, size_t off[8]) {
+void ws_layout(const RunTarget& t, int R, size_t* total, size_t off[9]) {
   const size_t st = align256((size_t)t.E * t.np * R * state_bytes(t.prec));
   size_t o = 0;
   off[0] = o; o += st;                                            // U
@@ -381,6 +461,8 @@ void ws_layout(const RunTarget& t, int R, size_t* total, size_t off[8]) {
   off[5] = o; o += align256((size_t)t.G * R * 6 * 8);             // moments
   off[6] = o; o += align256((size_t)(t.G + 1) * sizeof(int));     // block ranges
   off[7] = o; o += 256;                                           // step counter
+  off[8] = o;                                                     // q (mixed form)
+  if (t.form == 1) o += align256((size_t)t.E * 2 * t.np * R * state_bytes(t.prec));
   *total = o;
 }
 
@@ -412,6 +494,8 @@ void init_point_mass(dgd_run* run) {
       const double x = run->x0[((size_t)g * R + r) * 2] / m.h;
       const double y = run->x0[((size_t)g * R + r) * 2 + 1] / m.h;
       const int i = std::min(m.N - 1, (int)std::floor(x)), j = std::min(m.N - 1, (int)std::floor(y));
+      if (t.axon_host && t.axon_host[(size_t)j * m.N + i])
+        fail(DGD_ENOTFREE, "start point " + std::to_string((size_t)g * R + r) + " lies in an axon cell");
       fx[r] = x - i;
       fy[r] = y - j;
       want[((int64_t)j * m.N + i) * 2 + (fx[r] >= fy[r] ? 0 : 1)].push_back(r);
@@ -457,7 +541,7 @@ void init_point_mass(dgd_run* run) {
 // point mass).
 dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, void* d_ws,
                     size_t ws_bytes, void* hip_stream) {
-  size_t total, off[8];
+  size_t total, off[9];
   ws_layout(t, R, &total, off);
   auto* run = new dgd_run();
   try {
@@ -488,6 +572,7 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
     run->d_mom = (double*)(base + off[5]);
     run->d_blk_start = (int*)(base + off[6]);
     run->d_step = (uint32_t*)(base + off[7]);
+    if (t.form == 1) run->t.qbuf = base + off[8];
     DGD_HIP_CHECK(hipMemsetAsync(run->d_step, 0, sizeof(uint32_t), run->stream));
     if (!t.blk_start) {
       // one geometry: all reduction blocks
@@ -502,7 +587,7 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
                                  hipMemcpyHostToDevice, run->stream));
     // the stage launch shape, tuned on first use of its key (the two stage
     // buffers are free until the first step)
-    if (g_opt.autotune) tune_target(t, R, run->U1, run->U2, run->U, run->stream, false);
+    if (g_opt.autotune && t.form == 0) tune_target(t, R, run->U1, run->U2, run->U, run->stream, false);
     run->kind = (int)stage_kind(t, R);
     run->sh = pick_shape(t, R, (StageKind)run->kind);
     if (sigma0 == 0) {
@@ -510,10 +595,13 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
       return run;
     }
     const Shape shr = reduce_shape(t.E);
-    launch_ic_mass(t.np, t.elem, t.E, t.quad, t.nq, run->d_x0, t.blk_geom, sigma0, t.h, kCutoff, R,
+    // the mixed form keeps the axon cells; the pulse is restricted to the
+    // extracellular ones (axon elements enter as padding)
+    const int4* eic = t.elem_ic ? t.elem_ic : t.elem;
+    launch_ic_mass(t.np, eic, t.E, t.quad, t.nq, run->d_x0, t.blk_geom, sigma0, t.h, kCutoff, R,
                    shr, run->d_part, run->stream);
     launch_reduce(run->d_part, run->d_blk_start, t.G, R, run->d_mom, run->stream);
-    launch_ic_project(t.prec == DGD_FP64 ? 0 : 1, t.np, t.elem, t.E, t.quad, t.nq, t.Minv,
+    launch_ic_project(t.prec == DGD_FP64 ? 0 : 1, t.np, eic, t.E, t.quad, t.nq, t.Minv,
                       run->d_x0, t.blk_geom, run->d_mom, sigma0, t.h, kCutoff, R, shr, run->U,
                       run->stream);
     DGD_HIP_CHECK(hipGetLastError());
@@ -681,6 +769,18 @@ void check_points(const MeshHost& mh, const double* points, int n, int offset = 
   }
 }
 
+// Mixed form: start points must lie in extracellular cells.
+void check_axon_cells(const dgd_op* op, const double* points, int n) {
+  if (op->axon_cell.empty()) return;
+  const MeshHost& mh = op->mesh->host;
+  for (int r = 0; r < n; ++r) {
+    const int i = std::min(mh.N - 1, (int)(points[2 * r] / mh.h));
+    const int j = std::min(mh.N - 1, (int)(points[2 * r + 1] / mh.h));
+    if (op->axon_cell[(size_t)j * mh.N + i])
+      fail(DGD_ENOTFREE, "start point " + std::to_string(r) + " lies in an axon cell");
+  }
+}
+
 std::vector<std::pair<int64_t, double>> schedule(const double* deltas, int n, double dt_nom) {
   std::vector<std::pair<int64_t, double>> s;
   double prev = 0;
@@ -745,6 +845,8 @@ void batch_destroy(dgd_batch* b) {
 
 // Group geometries by p (each group shares one step size).
 void batch_plan(dgd_batch* b) {
+  for (int g = 0; g < b->G; ++g)
+    if (b->ops[g]->form != 0) fail(DGD_EINVAL, "batches take primal (removed-cell) operators only");
   for (int g = 0; g < b->G; ++g) {
     const int p = b->ops[g]->ref.p;
     auto it = std::find_if(b->groups.begin(), b->groups.end(),
@@ -770,7 +872,7 @@ size_t batch_group_bytes(const dgd_batch::Group& grp, const dgd_batch* b, RunTar
   t.E = E;
   t.G = (int)grp.geoms.size();
   t.nblk_red = E / kReducePer;
-  size_t total, off[8];
+  size_t total, off[9];
   ws_layout(t, b->R, &total, off);
   if (t_out) *t_out = t;
   return total;
@@ -980,8 +1082,12 @@ int dgd_operator_build(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, dou
                                   DGD_OUTER_REFLECT, out);
 }
 
-int dgd_operator_build_outer(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, double eta,
-                             int32_t precision, double dt_max_ms, int32_t outer, dgd_op** out) {
+// Operator build shared by the entry points: form 0 is the primal SIPG
+// operator (outer condition `outer`), form 1 the mixed form with k = 0 in
+// the cells of `disks`.
+static int build_operator(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, double eta,
+                   int32_t precision, double dt_max_ms, int32_t outer, int form,
+                   const double* disks, int32_t n_disks, dgd_op** out) {
   return guarded([&]() -> int {
     if (!out) fail(DGD_EINVAL, "out is NULL");
     if (outer != DGD_OUTER_REFLECT && outer != DGD_OUTER_ABSORB)
@@ -1021,7 +1127,8 @@ int dgd_operator_build_outer(const dgd_mesh* mesh, int32_t p, double D_um2_per_m
       for (size_t k = 0; k < Mp.size(); ++k) Mp[k] = R.Mass[k] * h * h;
       op->d_W = (double*)upload(Wp);
       op->d_Mass = (double*)upload(Mp);
-      if (p == 3 && precision == DGD_FP32) build_p3_tables(op);
+      if (p == 3 && precision == DGD_FP32 && form == 0) build_p3_tables(op);
+      if (form == 1) build_mixed_tables(op, disks, n_disks);
       op->quad = build_ic_quadrature(R, kQuadN);
       op->nq = kQuadN * kQuadN;
       op->d_quad = (double*)upload(op->quad);
@@ -1041,6 +1148,29 @@ int dgd_operator_build_outer(const dgd_mesh* mesh, int32_t p, double D_um2_per_m
     *out = op;
     return DGD_OK;
   });
+}
+
+int dgd_operator_build_outer(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, double eta,
+                             int32_t precision, double dt_max_ms, int32_t outer, dgd_op** out) {
+  return build_operator(mesh, p, D_um2_per_ms, eta, precision, dt_max_ms, outer, 0, nullptr, 0, out);
+}
+
+int dgd_operator_build_mixed(const dgd_mesh* mesh, const double* disks, int32_t n_disks, int32_t p,
+                             double D_um2_per_ms, int32_t precision, double dt_max_ms,
+                             dgd_op** out) {
+  if (n_disks < 0 || (n_disks > 0 && !disks)) {
+    set_error(DGD_EINVAL, "bad disk list");
+    return DGD_EINVAL;
+  }
+  for (int d = 0; d < n_disks; ++d)
+    if (!std::isfinite(disks[3 * d]) || !std::isfinite(disks[3 * d + 1]) ||
+        !std::isfinite(disks[3 * d + 2])) {
+      set_error(DGD_EINVAL, "non-finite disk");
+      return DGD_EINVAL;
+    }
+  // the penalty of the primal matrices built alongside is unused
+  return build_operator(mesh, p, D_um2_per_ms, 10.0, precision, dt_max_ms, DGD_OUTER_REFLECT, 1,
+                        disks, n_disks, out);
 }
 
 int dgd_operator_dt(const dgd_op* op, double* dt_nom_ms, double* lambda_max_per_ms) {
@@ -1066,7 +1196,7 @@ int dgd_workspace_size(const dgd_op* op, int32_t n_points, size_t* bytes) {
   return guarded([&]() -> int {
     if (!op || !bytes) fail(DGD_EINVAL, "NULL argument");
     if (n_points < 1) fail(DGD_EINVAL, "n_points must be >= 1");
-    size_t off[8];
+    size_t off[9];
     ws_layout(plain_target(op), n_points, bytes, off);
     return DGD_OK;
   });
@@ -1078,11 +1208,27 @@ int dgd_operator_apply(dgd_op* op, const void* d_in, void* d_out, int32_t n_rhs,
     if (n_rhs < 1) fail(DGD_EINVAL, "n_rhs must be >= 1");
     if (d_in == d_out) fail(DGD_EINVAL, "input and output must not overlap");
     const double h = op->mesh->host.h;
-    const RunTarget t = plain_target(op);
+    RunTarget t = plain_target(op);
     const StageKind kind = stage_kind(t, n_rhs);
-    stage(t, kind, pick_shape(t, n_rhs, kind), d_in, nullptr, d_out, 0, 0.0, op->D / (h * h), n_rhs,
-          (hipStream_t)hip_stream);
-    DGD_HIP_CHECK(hipGetLastError());
+    void* q = nullptr;
+    if (t.form == 1) {
+      // the gradient pass needs [E][2][np][n_rhs] scratch: allocated per call
+      DGD_HIP_CHECK(hipMalloc(&q, (size_t)t.E * 2 * t.np * n_rhs * state_bytes(t.prec)));
+      t.qbuf = q;
+    }
+    try {
+      stage(t, kind, pick_shape(t, n_rhs, kind), d_in, nullptr, d_out, 0, 0.0, op->D / (h * h),
+            n_rhs, (hipStream_t)hip_stream);
+      DGD_HIP_CHECK(hipGetLastError());
+      if (q) DGD_HIP_CHECK(hipStreamSynchronize((hipStream_t)hip_stream));
+    } catch (...) {
+      if (q) {
+        (void)hipStreamSynchronize((hipStream_t)hip_stream);
+        (void)hipFree(q);
+      }
+      throw;
+    }
+    if (q) DGD_HIP_CHECK(hipFree(q));
     return DGD_OK;
   });
 }
@@ -1093,6 +1239,11 @@ void dgd_operator_destroy(dgd_op* op) {
   (void)hipFree(op->d_N);
   (void)hipFree(op->d_F);
   (void)hipFree(op->d_B);
+  (void)hipFree(op->d_MG);
+  (void)hipFree(op->d_MD);
+  (void)hipFree(op->d_MN);
+  (void)hipFree(op->d_meta);
+  (void)hipFree(op->d_elem_ic);
   (void)hipFree(op->d_Minv);
   (void)hipFree(op->d_W);
   (void)hipFree(op->d_Mass);
@@ -1112,6 +1263,7 @@ int dgd_run_create(dgd_op* op, const double* points, int32_t n_points, double si
     if (n_points < 1) fail(DGD_EINVAL, "n_points must be >= 1");
     if (!(sigma0_um >= 0) || !std::isfinite(sigma0_um)) fail(DGD_EINVAL, "sigma0 must be >= 0");
     check_points(op->mesh->host, points, n_points);
+    check_axon_cells(op, points, n_points);
     *out = run_create(plain_target(op), points, n_points, sigma0_um, d_ws, ws_bytes, hip_stream);
     return DGD_OK;
   });
@@ -1288,6 +1440,8 @@ int dgd_eap_solve_expm(dgd_op* op, const double* points, int32_t n_points, doubl
     if (!op || !points || !deltas_ms || !sigma_out) fail(DGD_EINVAL, "NULL argument");
     if (n_points < 1 || n_deltas < 1) fail(DGD_EINVAL, "bad counts");
     if (!(sigma0_um >= 0) || !std::isfinite(sigma0_um)) fail(DGD_EINVAL, "sigma0 must be >= 0");
+    if (op->form != 0)
+      fail(DGD_EINVAL, "the Chebyshev exponential needs a real spectrum: primal operators only");
     schedule(deltas_ms, n_deltas, 1.0);  // validates the list
     check_points(op->mesh->host, points, n_points);
     double b = lambda_bound;

@@ -54,6 +54,15 @@ struct RefElem {
                                     //   sum over faces f not in mask of Fs_{o,f}
   std::vector<double> Bd;           // [2][3][np][np]  -M^-1 Fdir_f: face f on the absorbing box
                                     //   (u = 0 outside, Nitsche terms)
+  // the paper's mixed form (q = grad u with the central u-flux lifting,
+  // u_t = div(k q) with the harmonic-mean q-flux), dimensionless:
+  //   MG[o][mask][c] = M^-1 (G_c - sum_{f in mask} 1/2 n_{f,c} Ps_f)   q from own nodes
+  //   MD[o][mask][c] = M^-1 (-G_c^T + sum_{f in mask} 1/2 n_{f,c} Ps_f) u_t from own q
+  //   MN[o][f][c]    = M^-1 1/2 n_{f,c} Pn_f      neighbour nodes (both passes)
+  // G_c[i][j] = int (d phi_j / d x_c) phi_i, Ps_f / Pn_f the face mass with
+  // the own / neighbour basis, n the outward unit normal.
+  std::vector<double> MG, MD;       // [2][8][2][np][np]
+  std::vector<double> MN;           // [2][3][2][np][np]
   std::vector<double> Mass;         // [2][np][np]
   std::vector<double> Minv;         // [2][np][np]
   std::vector<double> W;            // [2][6][np] int phi_j xi^a eta^b over the triangle,
@@ -92,6 +101,14 @@ struct dgd_op {
   void* d_F = nullptr;    // [2][3][np][np] FP64 self-face blocks (packed stage kernel)
   int outer = DGD_OUTER_REFLECT;
   void* d_B = nullptr;    // [2][3][np][np] FP64 absorbing-box face blocks (DGD_OUTER_ABSORB)
+  // mixed form (dgd_operator_build_mixed): k = 0 in axon cells, kept in the mesh
+  int form = 0;
+  void* d_MG = nullptr;
+  void* d_MD = nullptr;
+  void* d_MN = nullptr;
+  uint8_t* d_meta = nullptr;
+  int4* d_elem_ic = nullptr;
+  std::vector<uint8_t> axon_cell;   // [j * N + i]
   double* d_Minv = nullptr;  // [2][np][np] FP64
   double* d_W = nullptr;     // [2][6][np] FP64 physical moment weights
   double* d_Mass = nullptr;  // [2][np][np] FP64 physical mass
@@ -133,6 +150,15 @@ struct RunTarget {
   const double* Wtab = nullptr;
   double wsum = 0;
   const RefElem* ref = nullptr;  // reference element (host)
+  // the paper's mixed form on all pixels (form 1; form 0: primal SIPG)
+  int form = 0;
+  const void* MG = nullptr;      // FP64 [2][8][2][np][np]
+  const void* MD = nullptr;      // FP64 [2][8][2][np][np]
+  const void* MN = nullptr;      // FP64 [2][3][2][np][np]
+  const uint8_t* meta = nullptr; // device [E] q-flux face mask | 8 if extracellular
+  const int4* elem_ic = nullptr; // element table with axon cells as padding (initial data)
+  const uint8_t* axon_host = nullptr;  // host [N * N] 1 = axon cell (form 1)
+  void* qbuf = nullptr;          // scratch q of the run, [E][2][np][R]
   // host mesh of each geometry and the row of its first element in the table
   std::vector<std::pair<const MeshHost*, int64_t>> hosts;
 };

@@ -247,6 +247,195 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
   }
 }
 
+// The paper's mixed form (eq. (6)-(7), fluxes of section 3.2) on all
+// pixels, as two passes per stage.
+//
+// Pass 1 (k_mixed_grad): per element K and right-hand side r, the scaled
+// gradient qh = h q = MG_{o,mask}(u_K - c) + sum_{f in mask} MN_{o,f}(u_f - c)
+// for both components (c = u_K[node 0]: G annihilates constants, so a
+// constant field gives exactly q = 0).  mask: faces with a neighbour element
+// (axon cells included: the central u-flux reads their value).  Stored in
+// the state type, round to nearest, layout [E][2][NP][R].
+//
+// Pass 2 (k_mixed_div): u_t = (D / h^2) (MD_{o,fm} qh_K + sum_{f in fm}
+// MN_{o,f} qh_f) on extracellular elements, zero on axon elements (k = 0);
+// fm: faces whose both sides are extracellular (the harmonic mean of k is
+// zero otherwise).  meta[e] = fm | extracellular << 3.  The stage combine and
+// the stochastic rounding of FP32 stores are those of k_stage (modes 0, 1).
+template <typename TS, int NP>
+__global__ void __launch_bounds__(256) k_mixed_grad(const TS* __restrict__ us, TS* __restrict__ qout,
+                                                    const int4* __restrict__ elem, int64_t E,
+                                                    const double* __restrict__ MG,
+                                                    const double* __restrict__ MN, int R, int epw,
+                                                    int64_t nblocks, int remap) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int r_raw = blockIdx.y * WAVE + lane;
+  const bool live = r_raw < R;
+  const int r = live ? r_raw : R - 1;
+  const BlockIter it = block_iter(nblocks, remap);
+  for (int64_t b = it.first; b < it.end; b += it.stride) {
+    const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
+    const int64_t e1 = e0 + epw < E ? e0 + epw : E;
+    for (int64_t e = e0; e < e1; ++e) {
+      const int4 m = elem[e];
+      const int o = m.w & 1;
+      const int mask = (m.w >> 1) & 7;
+      const int64_t self = (e * NP) * (int64_t)R + r;
+      const int64_t n0 = (m.x >= 0 ? (int64_t)m.x * NP * R + r : self);
+      const int64_t n1 = (m.y >= 0 ? (int64_t)m.y * NP * R + r : self);
+      const int64_t n2 = (m.z >= 0 ? (int64_t)m.z * NP * R + r : self);
+      TS su[NP], s0[NP], s1[NP], s2[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        su[j] = us[self + (int64_t)j * R];
+        s0[j] = us[n0 + (int64_t)j * R];
+        s1[j] = us[n1 + (int64_t)j * R];
+        s2[j] = us[n2 + (int64_t)j * R];
+      }
+      const double c = (double)su[0];
+      double d[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) d[j] = (double)su[j] - c;
+      double ax[NP], ay[NP];
+      {
+        const double* Gx = MG + ((o * 8 + mask) * 2 + 0) * NP * NP;
+        const double* Gy = MG + ((o * 8 + mask) * 2 + 1) * NP * NP;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          double a = 0.0, bb = 0.0;
+#pragma unroll
+          for (int j = 0; j < NP; ++j) {
+            a = fma(Gx[i * NP + j], d[j], a);
+            bb = fma(Gy[i * NP + j], d[j], bb);
+          }
+          ax[i] = a;
+          ay[i] = bb;
+        }
+      }
+#define DGD_MFACE(F, SV)                                                                    \
+      if (mask & (1 << F)) {                                                                \
+        const double* Nx = MN + ((o * 3 + F) * 2 + 0) * NP * NP;                            \
+        const double* Ny = MN + ((o * 3 + F) * 2 + 1) * NP * NP;                            \
+        double dn[NP];                                                                      \
+        _Pragma("unroll") for (int j = 0; j < NP; ++j) dn[j] = (double)SV[j] - c;           \
+        _Pragma("unroll") for (int i = 0; i < NP; ++i) {                                    \
+          double a = ax[i], bb = ay[i];                                                     \
+          _Pragma("unroll") for (int j = 0; j < NP; ++j) {                                  \
+            a = fma(Nx[i * NP + j], dn[j], a);                                              \
+            bb = fma(Ny[i * NP + j], dn[j], bb);                                            \
+          }                                                                                 \
+          ax[i] = a;                                                                        \
+          ay[i] = bb;                                                                       \
+        }                                                                                   \
+      }
+      DGD_MFACE(0, s0)
+      DGD_MFACE(1, s1)
+      DGD_MFACE(2, s2)
+#undef DGD_MFACE
+      if (!live) continue;
+      const int64_t qb = (e * 2 * NP) * (int64_t)R + r;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        qout[qb + (int64_t)i * R] = (TS)ax[i];
+        qout[qb + (int64_t)(NP + i) * R] = (TS)ay[i];
+      }
+    }
+  }
+}
+
+template <typename TS, int NP>
+__global__ void __launch_bounds__(256) k_mixed_div(const TS* __restrict__ q, const TS* __restrict__ us,
+                                                   const TS* ub, TS* out,
+                                                   const int4* __restrict__ elem,
+                                                   const uint8_t* __restrict__ meta, int64_t E,
+                                                   const double* __restrict__ MD,
+                                                   const double* __restrict__ MN, int mode,
+                                                   double cb, double cg, int R, int epw,
+                                                   int64_t nblocks, int remap,
+                                                   const uint32_t* step, int stage_id) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int r_raw = blockIdx.y * WAVE + lane;
+  const bool live = r_raw < R;
+  const int r = live ? r_raw : R - 1;
+  const bool use_base = ub != nullptr;
+  const uint32_t smix = step_mix(step, stage_id);
+  const BlockIter it = block_iter(nblocks, remap);
+  for (int64_t b = it.first; b < it.end; b += it.stride) {
+    const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
+    const int64_t e1 = e0 + epw < E ? e0 + epw : E;
+    for (int64_t e = e0; e < e1; ++e) {
+      const int4 m = elem[e];
+      const int o = m.w & 1;
+      const int mt = meta[e];
+      const int fm = mt & 7;
+      const bool ext = (mt >> 3) & 1;
+      const int64_t self = (e * NP) * (int64_t)R + r;
+      double acc[NP];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) acc[i] = 0.0;
+      if (ext) {
+        const int64_t qs = (e * 2 * NP) * (int64_t)R + r;
+        double qx[NP], qy[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+          qx[j] = (double)q[qs + (int64_t)j * R];
+          qy[j] = (double)q[qs + (int64_t)(NP + j) * R];
+        }
+        const double* Dx = MD + ((o * 8 + fm) * 2 + 0) * NP * NP;
+        const double* Dy = MD + ((o * 8 + fm) * 2 + 1) * NP * NP;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          double a = 0.0;
+#pragma unroll
+          for (int j = 0; j < NP; ++j) a = fma(Dx[i * NP + j], qx[j], fma(Dy[i * NP + j], qy[j], a));
+          acc[i] = a;
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          if (!((fm >> f) & 1)) continue;
+          const int nb = f == 0 ? m.x : (f == 1 ? m.y : m.z);
+          const int64_t qn = ((int64_t)nb * 2 * NP) * R + r;
+#pragma unroll
+          for (int j = 0; j < NP; ++j) {
+            qx[j] = (double)q[qn + (int64_t)j * R];
+            qy[j] = (double)q[qn + (int64_t)(NP + j) * R];
+          }
+          const double* Nx = MN + ((o * 3 + f) * 2 + 0) * NP * NP;
+          const double* Ny = MN + ((o * 3 + f) * 2 + 1) * NP * NP;
+#pragma unroll
+          for (int i = 0; i < NP; ++i) {
+            double a = acc[i];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) a = fma(Nx[i * NP + j], qx[j], fma(Ny[i * NP + j], qy[j], a));
+            acc[i] = a;
+          }
+        }
+      }
+      if (!live) continue;
+      if (mode == 0) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)(cg * acc[i]);
+      } else if (use_base) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          const double u = (double)us[self + (int64_t)i * R];
+          const double b0 = (double)ub[self + (int64_t)i * R];
+          store_state(out, self + (int64_t)i * R, b0 + cb * (u - b0) + cg * acc[i],
+                      state_salt(m.w, i * R + r, smix));
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          const double u = (double)us[self + (int64_t)i * R];
+          store_state(out, self + (int64_t)i * R, u + cg * acc[i], state_salt(m.w, i * R + r, smix));
+        }
+      }
+    }
+  }
+}
+
 // P3 stage on matrix cores (FP32 state, R a multiple of 16).  For element K
 // of class (o, mask) the contraction over the stacked stencil
 //   L(u)_K = [S_{o,mask} | N_{o,0} | N_{o,1} | N_{o,2}] (u_stencil - c)
@@ -970,6 +1159,33 @@ void launch_stage(int prec, int np, const void* us, const void* ub, void* out, c
 
 void launch_step_bump(uint32_t* step, hipStream_t st) {
   hipLaunchKernelGGL(k_step_bump, dim3(1), dim3(64), 0, st, step);
+}
+
+template <typename T, int NP>
+void mixed_stage_t(const void* us, const void* ub, void* out, void* q, const int4* elem,
+                   const uint8_t* meta, int64_t E, const void* MG, const void* MD, const void* MN,
+                   int mode, double cb, double cg, int R, const Shape& sh, const uint32_t* step,
+                   int stage_id, hipStream_t st) {
+  const unsigned chunks = (unsigned)((R + 63) / 64);
+  const dim3 grid((unsigned)sh.grid, chunks), block(64 * sh.waves);
+  hipLaunchKernelGGL((k_mixed_grad<T, NP>), grid, block, 0, st, (const T*)us, (T*)q, elem, E,
+                     (const double*)MG, (const double*)MN, R, sh.epw, sh.blocks, sh.remap ? 1 : 0);
+  hipLaunchKernelGGL((k_mixed_div<T, NP>), grid, block, 0, st, (const T*)q, (const T*)us,
+                     (const T*)ub, (T*)out, elem, meta, E, (const double*)MD, (const double*)MN,
+                     mode, cb, cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0, step, stage_id);
+}
+
+void launch_mixed_stage(int prec, int np, const void* us, const void* ub, void* out, void* q,
+                        const int4* elem, const uint8_t* meta, int64_t E, const void* MG,
+                        const void* MD, const void* MN, int mode, double cb, double cg, int R,
+                        const Shape& sh, hipStream_t st, const uint32_t* step, int stage_id) {
+  if (prec == 0) {
+    DGD_DISPATCH_NP(np, mixed_stage_t<double, NP>(us, ub, out, q, elem, meta, E, MG, MD, MN, mode,
+                                                  cb, cg, R, sh, step, stage_id, st));
+  } else {
+    DGD_DISPATCH_NP(np, mixed_stage_t<float, NP>(us, ub, out, q, elem, meta, E, MG, MD, MN, mode,
+                                                 cb, cg, R, sh, step, stage_id, st));
+  }
 }
 
 void launch_ic_point(int prec, const int64_t* pe, const int* col, const double* vals, int n, int np,

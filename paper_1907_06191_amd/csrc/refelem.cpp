@@ -230,9 +230,12 @@ RefElem build_ref_elem(int p, double eta) {
   R.Mass.assign(2 * np * np, 0);
   R.Minv.assign(2 * np * np, 0);
   R.W.assign(2 * 6 * np, 0);
+  R.MG.assign(2 * 8 * 2 * np * np, 0);
+  R.MD.assign(2 * 8 * 2 * np * np, 0);
+  R.MN.assign(2 * 3 * 2 * np * np, 0);
   std::vector<double> v(np), vx(np), vy(np), w2(np), wx(np), wy(np);
   for (int o = 0; o < 2; ++o) {
-    std::vector<double> M(np * np, 0), K(np * np, 0);
+    std::vector<double> M(np * np, 0), K(np * np, 0), GX(np * np, 0), GY(np * np, 0);
     for (size_t q = 0; q < qw.size(); ++q) {
       double x, y;
       if (o == 0) { x = qr[q] + qs[q]; y = qs[q]; } else { x = qr[q]; y = qr[q] + qs[q]; }
@@ -243,16 +246,20 @@ RefElem build_ref_elem(int p, double eta) {
         for (int j = 0; j < np; ++j) {
           M[i * np + j] += qw[q] * v[i] * v[j];
           K[i * np + j] += qw[q] * (vx[i] * vx[j] + vy[i] * vy[j]);
+          GX[i * np + j] += qw[q] * vx[j] * v[i];
+          GY[i * np + j] += qw[q] * vy[j] * v[i];
         }
         for (int a = 0; a < 6; ++a) R.W[(o * 6 + a) * np + i] += qw[q] * pw[a] * v[i];
       }
     }
     const std::vector<double> Mi = inverse(M, np);
-    std::vector<double> Fs[3], Fn[3], Fd[3];
+    std::vector<double> Fs[3], Fn[3], Fd[3], Ps[3], Pn[3];
     for (int f = 0; f < 3; ++f) {
       Fs[f].assign(np * np, 0);
       Fn[f].assign(np * np, 0);
       Fd[f].assign(np * np, 0);
+      Ps[f].assign(np * np, 0);
+      Pn[f].assign(np * np, 0);
       const double ex = P1[o][f][0] - P0[o][f][0], ey = P1[o][f][1] - P0[o][f][1];
       const double len = std::sqrt(ex * ex + ey * ey);
       const double nx = NRM[o][f][0], ny = NRM[o][f][1];
@@ -270,7 +277,42 @@ RefElem build_ref_elem(int p, double eta) {
             Fn[f][i * np + j] += wq * (-0.5 * dnj_n * v[i] + 0.5 * dni * w2[j] - pen * v[i] * w2[j]);
             // face on the absorbing box: the same terms with zero outside value
             Fd[f][i * np + j] += wq * (-dnj * v[i] - dni * v[j] + pen * v[i] * v[j]);
+            Ps[f][i * np + j] += wq * v[i] * v[j];
+            Pn[f][i * np + j] += wq * v[i] * w2[j];
           }
+      }
+    }
+    // mixed form
+    auto mi_times = [&](const std::vector<double>& A, double* dst) {
+      for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) {
+          double acc = 0;
+          for (int k = 0; k < np; ++k) acc += Mi[i * np + k] * A[k * np + j];
+          dst[i * np + j] = acc;
+        }
+    };
+    for (int c = 0; c < 2; ++c) {
+      const std::vector<double>& Gc = c == 0 ? GX : GY;
+      for (int mask = 0; mask < 8; ++mask) {
+        std::vector<double> Tg(np * np), Td(np * np);
+        for (int i = 0; i < np; ++i)
+          for (int j = 0; j < np; ++j) {
+            Tg[i * np + j] = Gc[i * np + j];
+            Td[i * np + j] = -Gc[j * np + i];
+          }
+        for (int f = 0; f < 3; ++f)
+          if (mask >> f & 1)
+            for (int k = 0; k < np * np; ++k) {
+              Tg[k] -= 0.5 * NRM[o][f][c] * Ps[f][k];
+              Td[k] += 0.5 * NRM[o][f][c] * Ps[f][k];
+            }
+        mi_times(Tg, &R.MG[(((size_t)o * 8 + mask) * 2 + c) * np * np]);
+        mi_times(Td, &R.MD[(((size_t)o * 8 + mask) * 2 + c) * np * np]);
+      }
+      for (int f = 0; f < 3; ++f) {
+        std::vector<double> Tn(np * np);
+        for (int k = 0; k < np * np; ++k) Tn[k] = 0.5 * NRM[o][f][c] * Pn[f][k];
+        mi_times(Tn, &R.MN[(((size_t)o * 3 + f) * 2 + c) * np * np]);
       }
     }
     for (int mask = 0; mask < 8; ++mask) {

@@ -72,6 +72,8 @@ _sig("dgd_operator_build", [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_doubl
 _sig("dgd_operator_build_outer", [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                   ctypes.POINTER(_vp)])
+_sig("dgd_operator_build_mixed", [_vp, _c_dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                  ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_vp)])
 _sig("dgd_operator_dt", [_vp, _c_dp, _c_dp])
 _sig("dgd_operator_info", [_vp, ctypes.POINTER(ctypes.c_int32), _c_dp, ctypes.POINTER(ctypes.c_int32)])
 _sig("dgd_workspace_size", [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)])
@@ -234,6 +236,16 @@ def dgd_operator_build_outer(mesh, p: int, D: float, eta: float, precision: int,
     out = _vp()
     _check(_lib.dgd_operator_build_outer(mesh, int(p), float(D), float(eta), int(precision),
                                          float(dt_max_ms), int(outer), ctypes.byref(out)))
+    return out.value
+
+
+def dgd_operator_build_mixed(mesh, disks, p: int, D: float, precision: int,
+                             dt_max_ms: float = 0.0) -> int:
+    d = _f64(disks).reshape(-1, 3) if disks is not None else np.zeros((0, 3))
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = _vp()
+    _check(_lib.dgd_operator_build_mixed(mesh, _ptr(d), int(d.shape[0]), int(p), float(D),
+                                         int(precision), float(dt_max_ms), ctypes.byref(out)))
     return out.value
 
 
@@ -567,6 +579,17 @@ class Operator:
 
     def __del__(self):
         self.close()
+
+
+class MixedOperator(Operator):
+    """The paper's mixed form on all pixels (k = 0 in the cells of `disks`);
+    `mesh` normally holds every pixel (built with no disks)."""
+
+    def __init__(self, mesh: Mesh, disks, p, D, precision, dt_max_ms=0.0):
+        self._destroy = _lib.dgd_operator_destroy
+        self.mesh = mesh
+        self.outer = DGD_OUTER_REFLECT
+        self.handle = dgd_operator_build_mixed(mesh.handle, disks, p, D, precision, dt_max_ms)
 
 
 class Batch:
