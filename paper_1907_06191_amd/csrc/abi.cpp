@@ -572,7 +572,14 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
     run->d_mom = (double*)(base + off[5]);
     run->d_blk_start = (int*)(base + off[6]);
     run->d_step = (uint32_t*)(base + off[7]);
-    if (t.form == 1) run->t.qbuf = base + off[8];
+    if (t.form == 1) {
+      run->t.qbuf = base + off[8];
+      // the stage kernels skip axon elements (u = 0 there): the stage
+      // buffers start at zero
+      const size_t sb = (size_t)t.E * t.np * R * state_bytes(t.prec);
+      DGD_HIP_CHECK(hipMemsetAsync(run->U1, 0, sb, run->stream));
+      DGD_HIP_CHECK(hipMemsetAsync(run->U2, 0, sb, run->stream));
+    }
     DGD_HIP_CHECK(hipMemsetAsync(run->d_step, 0, sizeof(uint32_t), run->stream));
     if (!t.blk_start) {
       // one geometry: all reduction blocks
@@ -1309,7 +1316,20 @@ int dgd_run_get_state(dgd_run* run, void* host_out) {
 int dgd_run_set_state(dgd_run* run, const void* host_in) {
   return guarded([&]() -> int {
     if (!run || !host_in) fail(DGD_EINVAL, "NULL argument");
-    const size_t n = (size_t)run->t.E * run->t.np * run->R * state_bytes(run->t.prec);
+    const RunTarget& t = run->t;
+    const size_t n = (size_t)t.E * t.np * run->R * state_bytes(t.prec);
+    if (t.form == 1) {
+      // mixed form: u is zero in axon cells (k = 0, no flux in); the stage
+      // kernels never touch those blocks, so they are cleared here
+      const MeshHost& m = *t.hosts[0].first;
+      const size_t blk = (size_t)t.np * run->R * state_bytes(t.prec);
+      std::vector<char> buf((const char*)host_in, (const char*)host_in + n);
+      for (int64_t e = 0; e < t.E; ++e)
+        if (t.axon_host[(size_t)m.cj[e] * m.N + m.ci[e]]) std::memset(&buf[e * blk], 0, blk);
+      DGD_HIP_CHECK(hipMemcpyAsync(run->U, buf.data(), n, hipMemcpyHostToDevice, run->stream));
+      DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+      return DGD_OK;
+    }
     DGD_HIP_CHECK(hipMemcpyAsync(run->U, host_in, n, hipMemcpyHostToDevice, run->stream));
     DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
     return DGD_OK;

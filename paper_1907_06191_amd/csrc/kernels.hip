@@ -258,13 +258,17 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
 // the state type, round to nearest, layout [E][2][NP][R].
 //
 // Pass 2 (k_mixed_div): u_t = (D / h^2) (MD_{o,fm} qh_K + sum_{f in fm}
-// MN_{o,f} qh_f) on extracellular elements, zero on axon elements (k = 0);
+// MN_{o,f} qh_f) on extracellular elements, zero on axon elements (k = 0).
+// u is zero in axon cells and stays so: both passes skip axon elements
+// (the stage buffers are cleared once when a run is created), except that
+// the operator apply (mode 0) writes their zero derivative;
 // fm: faces whose both sides are extracellular (the harmonic mean of k is
 // zero otherwise).  meta[e] = fm | extracellular << 3.  The stage combine and
 // the stochastic rounding of FP32 stores are those of k_stage (modes 0, 1).
 template <typename TS, int NP>
 __global__ void __launch_bounds__(256) k_mixed_grad(const TS* __restrict__ us, TS* __restrict__ qout,
-                                                    const int4* __restrict__ elem, int64_t E,
+                                                    const int4* __restrict__ elem,
+                                                    const uint8_t* __restrict__ meta, int64_t E,
                                                     const double* __restrict__ MG,
                                                     const double* __restrict__ MN, int R, int epw,
                                                     int64_t nblocks, int remap) {
@@ -278,6 +282,8 @@ __global__ void __launch_bounds__(256) k_mixed_grad(const TS* __restrict__ us, T
     const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
     const int64_t e1 = e0 + epw < E ? e0 + epw : E;
     for (int64_t e = e0; e < e1; ++e) {
+      // q of an axon element is never read (its q-flux faces are all off)
+      if (!((meta[e] >> 3) & 1)) continue;
       const int4 m = elem[e];
       const int o = m.w & 1;
       const int mask = (m.w >> 1) & 7;
@@ -372,6 +378,15 @@ __global__ void __launch_bounds__(256) k_mixed_div(const TS* __restrict__ q, con
       const int fm = mt & 7;
       const bool ext = (mt >> 3) & 1;
       const int64_t self = (e * NP) * (int64_t)R + r;
+      // axon element: u stays zero (k = 0, no q-flux); only the operator
+      // apply (mode 0) writes its zero derivative
+      if (!ext) {
+        if (mode == 0 && live) {
+#pragma unroll
+          for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)0;
+        }
+        continue;
+      }
       double acc[NP];
 #pragma unroll
       for (int i = 0; i < NP; ++i) acc[i] = 0.0;
@@ -1168,7 +1183,7 @@ void mixed_stage_t(const void* us, const void* ub, void* out, void* q, const int
                    int stage_id, hipStream_t st) {
   const unsigned chunks = (unsigned)((R + 63) / 64);
   const dim3 grid((unsigned)sh.grid, chunks), block(64 * sh.waves);
-  hipLaunchKernelGGL((k_mixed_grad<T, NP>), grid, block, 0, st, (const T*)us, (T*)q, elem, E,
+  hipLaunchKernelGGL((k_mixed_grad<T, NP>), grid, block, 0, st, (const T*)us, (T*)q, elem, meta, E,
                      (const double*)MG, (const double*)MN, R, sh.epw, sh.blocks, sh.remap ? 1 : 0);
   hipLaunchKernelGGL((k_mixed_div<T, NP>), grid, block, 0, st, (const T*)q, (const T*)us,
                      (const T*)ub, (T*)out, elem, meta, E, (const double*)MD, (const double*)MN,
