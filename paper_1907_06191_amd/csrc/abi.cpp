@@ -143,6 +143,7 @@ RunTarget plain_target(const dgd_op* op) {
   t.MG = op->d_MG;
   t.MD = op->d_MD;
   t.MN = op->d_MN;
+  t.MNcol = op->d_MNcol;
   t.meta = op->d_meta;
   t.elem_ic = op->d_elem_ic;
   t.axon_host = op->axon_cell.empty() ? nullptr : op->axon_cell.data();
@@ -177,7 +178,7 @@ int64_t stage_units(const RunTarget& t, int R, StageKind k) {
 }
 
 std::string kind_key(const RunTarget& t, int R, StageKind k) {
-  return tune_key(t.np, t.prec, kKindName[k], R, t.E);
+  return tune_key(t.np, t.prec, t.form == 1 ? "mixed" : kKindName[k], R, t.E);
 }
 
 // The kernel for (t, R) without timing: the matrix cores when forced
@@ -198,7 +199,7 @@ StageKind stage_kind(const RunTarget& t, int R) {
 // options.
 Shape pick_shape(const RunTarget& t, int R, StageKind kind) {
   const int64_t units = stage_units(t, R, kind);
-  if (g_opt.autotune && t.form == 0) {
+  if (g_opt.autotune) {
     TuneParams p;
     if (tune_find(kind_key(t, R, kind), &p)) return tune_shape(p, units);
   }
@@ -211,7 +212,7 @@ void stage(const RunTarget& t, StageKind kind, const Shape& sh, const void* us, 
   if (t.form == 1) {
     if (!t.qbuf) fail(DGD_EINVAL, "internal: mixed-form stage without its q buffer");
     launch_mixed_stage(t.prec == DGD_FP64 ? 0 : 1, t.np, us, ub, out, t.qbuf, t.elem, t.meta, t.E,
-                       t.MG, t.MD, t.MN, mode, cb, cg, R, sh, st, step, stage_id);
+                       t.MG, t.MD, t.MN, t.MNcol, mode, cb, cg, R, sh, st, step, stage_id);
     return;
   }
   switch (kind) {
@@ -286,7 +287,8 @@ void build_mixed_tables(dgd_op* op, const double* disks, int n_disks) {
   op->d_elem_ic = (int4*)upload(eic);
   op->d_MG = upload(op->ref.MG);
   op->d_MD = upload(op->ref.MD);
-  op->d_MN = upload(op->ref.MN);
+  op->d_MN = upload(op->ref.MNc);
+  op->d_MNcol = (int*)upload(op->ref.MNcol);
   op->form = 1;
 }
 
@@ -395,7 +397,7 @@ double power_lambda(dgd_op* op, int iters) {
   auto apply = [&](const double* in, double* out, double cg, hipStream_t st) {
     if (op->form == 1)
       launch_mixed_stage(DGD_FP64, np, in, nullptr, out, q, mesh->d_elem, op->d_meta, E, op->d_MG,
-                         op->d_MD, op->d_MN, 0, 0.0, cg, R, sh, st);
+                         op->d_MD, op->d_MN, op->d_MNcol, 0, 0.0, cg, R, sh, st);
     else
       launch_stage(DGD_FP64, np, in, nullptr, out, mesh->d_elem, E, op->d_S, op->d_N, 0, 0.0, cg, R,
                    sh, st, nullptr, 0, op->d_B);
@@ -572,14 +574,7 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
     run->d_mom = (double*)(base + off[5]);
     run->d_blk_start = (int*)(base + off[6]);
     run->d_step = (uint32_t*)(base + off[7]);
-    if (t.form == 1) {
-      run->t.qbuf = base + off[8];
-      // the stage kernels skip axon elements (u = 0 there): the stage
-      // buffers start at zero
-      const size_t sb = (size_t)t.E * t.np * R * state_bytes(t.prec);
-      DGD_HIP_CHECK(hipMemsetAsync(run->U1, 0, sb, run->stream));
-      DGD_HIP_CHECK(hipMemsetAsync(run->U2, 0, sb, run->stream));
-    }
+    if (t.form == 1) run->t.qbuf = base + off[8];
     DGD_HIP_CHECK(hipMemsetAsync(run->d_step, 0, sizeof(uint32_t), run->stream));
     if (!t.blk_start) {
       // one geometry: all reduction blocks
@@ -594,7 +589,14 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
                                  hipMemcpyHostToDevice, run->stream));
     // the stage launch shape, tuned on first use of its key (the two stage
     // buffers are free until the first step)
-    if (g_opt.autotune && t.form == 0) tune_target(t, R, run->U1, run->U2, run->U, run->stream, false);
+    if (g_opt.autotune) tune_target(run->t, R, run->U1, run->U2, run->U, run->stream, false);
+    if (t.form == 1) {
+      // the mixed-form stage kernels skip axon elements (u = 0 there): the
+      // stage buffers start at zero (after the tuner used them as scratch)
+      const size_t sb = (size_t)t.E * t.np * R * state_bytes(t.prec);
+      DGD_HIP_CHECK(hipMemsetAsync(run->U1, 0, sb, run->stream));
+      DGD_HIP_CHECK(hipMemsetAsync(run->U2, 0, sb, run->stream));
+    }
     run->kind = (int)stage_kind(t, R);
     run->sh = pick_shape(t, R, (StageKind)run->kind);
     if (sigma0 == 0) {
@@ -938,14 +940,19 @@ int dgd_autotune(dgd_op* op, int32_t n_points, void* hip_stream, int32_t* shape_
   void* a = nullptr;
   void* b = nullptr;
   void* c = nullptr;
+  void* qb = nullptr;
   int rc = guarded([&]() -> int {
     if (!op) fail(DGD_EINVAL, "op is NULL");
     if (n_points < 1) fail(DGD_EINVAL, "n_points must be >= 1");
-    const RunTarget t = plain_target(op);
+    RunTarget t = plain_target(op);
     const size_t bytes = (size_t)t.E * t.np * n_points * state_bytes(t.prec);
     DGD_HIP_CHECK(hipMalloc(&a, bytes));
     DGD_HIP_CHECK(hipMalloc(&b, bytes));
     DGD_HIP_CHECK(hipMalloc(&c, bytes));
+    if (t.form == 1) {
+      DGD_HIP_CHECK(hipMalloc(&qb, 2 * bytes));
+      t.qbuf = qb;
+    }
     const int64_t n = (int64_t)(bytes / state_bytes(t.prec));
     if (t.prec == DGD_FP64)
       launch_fill_random((double*)c, n, 0xba5eull, (hipStream_t)hip_stream);
@@ -967,6 +974,7 @@ int dgd_autotune(dgd_op* op, int32_t n_points, void* hip_stream, int32_t* shape_
   (void)hipFree(a);
   (void)hipFree(b);
   (void)hipFree(c);
+  (void)hipFree(qb);
   return rc;
 }
 
@@ -1249,6 +1257,7 @@ void dgd_operator_destroy(dgd_op* op) {
   (void)hipFree(op->d_MG);
   (void)hipFree(op->d_MD);
   (void)hipFree(op->d_MN);
+  (void)hipFree(op->d_MNcol);
   (void)hipFree(op->d_meta);
   (void)hipFree(op->d_elem_ic);
   (void)hipFree(op->d_Minv);

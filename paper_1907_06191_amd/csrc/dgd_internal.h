@@ -63,6 +63,11 @@ struct RefElem {
   // the own / neighbour basis, n the outward unit normal.
   std::vector<double> MG, MD;       // [2][8][2][np][np]
   std::vector<double> MN;           // [2][3][2][np][np]
+  // MN keeps only the neighbour's p + 1 nodes on the shared face (a nodal
+  // basis function of a node off the face vanishes on it):
+  //   MNc[o][f][c][i][k] = MN[o][f][c][i][MNcol[o][f][k]],  k < p + 1
+  std::vector<double> MNc;          // [2][3][2][np][p+1]
+  std::vector<int32_t> MNcol;       // [2][3][p+1]
   std::vector<double> Mass;         // [2][np][np]
   std::vector<double> Minv;         // [2][np][np]
   std::vector<double> W;            // [2][6][np] int phi_j xi^a eta^b over the triangle,
@@ -105,7 +110,8 @@ struct dgd_op {
   int form = 0;
   void* d_MG = nullptr;
   void* d_MD = nullptr;
-  void* d_MN = nullptr;
+  void* d_MN = nullptr;          // compacted neighbour blocks
+  int* d_MNcol = nullptr;        // their columns
   uint8_t* d_meta = nullptr;
   int4* d_elem_ic = nullptr;
   std::vector<uint8_t> axon_cell;   // [j * N + i]
@@ -154,7 +160,8 @@ struct RunTarget {
   int form = 0;
   const void* MG = nullptr;      // FP64 [2][8][2][np][np]
   const void* MD = nullptr;      // FP64 [2][8][2][np][np]
-  const void* MN = nullptr;      // FP64 [2][3][2][np][np]
+  const void* MN = nullptr;      // FP64 [2][3][2][np][p+1] (face-node columns)
+  const int* MNcol = nullptr;    // int32 [2][3][p+1]
   const uint8_t* meta = nullptr; // device [E] q-flux face mask | 8 if extracellular
   const int4* elem_ic = nullptr; // element table with axon cells as padding (initial data)
   const uint8_t* axon_host = nullptr;  // host [N * N] 1 = axon cell (form 1)

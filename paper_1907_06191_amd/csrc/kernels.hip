@@ -254,7 +254,10 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
 // gradient qh = h q = MG_{o,mask}(u_K - c) + sum_{f in mask} MN_{o,f}(u_f - c)
 // for both components (c = u_K[node 0]: G annihilates constants, so a
 // constant field gives exactly q = 0).  mask: faces with a neighbour element
-// (axon cells included: the central u-flux reads their value).  Stored in
+// (axon cells included: the central u-flux reads their value).  MN is the
+// compacted neighbour block: a nodal basis function of a node off the
+// shared face vanishes on it, so a neighbour enters through its p + 1 face
+// nodes (columns MNcol) only.  Stored in
 // the state type, round to nearest, layout [E][2][NP][R].
 //
 // Pass 2 (k_mixed_div): u_t = (D / h^2) (MD_{o,fm} qh_K + sum_{f in fm}
@@ -270,8 +273,10 @@ __global__ void __launch_bounds__(256) k_mixed_grad(const TS* __restrict__ us, T
                                                     const int4* __restrict__ elem,
                                                     const uint8_t* __restrict__ meta, int64_t E,
                                                     const double* __restrict__ MG,
-                                                    const double* __restrict__ MN, int R, int epw,
+                                                    const double* __restrict__ MN,
+                                                    const int* __restrict__ MNcol, int R, int epw,
                                                     int64_t nblocks, int remap) {
+  constexpr int NF = NP == 3 ? 2 : (NP == 6 ? 3 : 4);    // nodes on a face (p + 1)
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int r_raw = blockIdx.y * WAVE + lane;
@@ -291,13 +296,18 @@ __global__ void __launch_bounds__(256) k_mixed_grad(const TS* __restrict__ us, T
       const int64_t n0 = (m.x >= 0 ? (int64_t)m.x * NP * R + r : self);
       const int64_t n1 = (m.y >= 0 ? (int64_t)m.y * NP * R + r : self);
       const int64_t n2 = (m.z >= 0 ? (int64_t)m.z * NP * R + r : self);
-      TS su[NP], s0[NP], s1[NP], s2[NP];
+      // a neighbour enters only through its nodes on the shared face
+      const int* c0 = MNcol + (o * 3 + 0) * NF;
+      const int* c1 = MNcol + (o * 3 + 1) * NF;
+      const int* c2 = MNcol + (o * 3 + 2) * NF;
+      TS su[NP], s0[NF], s1[NF], s2[NF];
 #pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        su[j] = us[self + (int64_t)j * R];
-        s0[j] = us[n0 + (int64_t)j * R];
-        s1[j] = us[n1 + (int64_t)j * R];
-        s2[j] = us[n2 + (int64_t)j * R];
+      for (int j = 0; j < NP; ++j) su[j] = us[self + (int64_t)j * R];
+#pragma unroll
+      for (int k = 0; k < NF; ++k) {
+        s0[k] = us[n0 + (int64_t)c0[k] * R];
+        s1[k] = us[n1 + (int64_t)c1[k] * R];
+        s2[k] = us[n2 + (int64_t)c2[k] * R];
       }
       const double c = (double)su[0];
       double d[NP];
@@ -321,15 +331,15 @@ __global__ void __launch_bounds__(256) k_mixed_grad(const TS* __restrict__ us, T
       }
 #define DGD_MFACE(F, SV)                                                                    \
       if (mask & (1 << F)) {                                                                \
-        const double* Nx = MN + ((o * 3 + F) * 2 + 0) * NP * NP;                            \
-        const double* Ny = MN + ((o * 3 + F) * 2 + 1) * NP * NP;                            \
-        double dn[NP];                                                                      \
-        _Pragma("unroll") for (int j = 0; j < NP; ++j) dn[j] = (double)SV[j] - c;           \
+        const double* Nx = MN + ((o * 3 + F) * 2 + 0) * NP * NF;                            \
+        const double* Ny = MN + ((o * 3 + F) * 2 + 1) * NP * NF;                            \
+        double dn[NF];                                                                      \
+        _Pragma("unroll") for (int k = 0; k < NF; ++k) dn[k] = (double)SV[k] - c;           \
         _Pragma("unroll") for (int i = 0; i < NP; ++i) {                                    \
           double a = ax[i], bb = ay[i];                                                     \
-          _Pragma("unroll") for (int j = 0; j < NP; ++j) {                                  \
-            a = fma(Nx[i * NP + j], dn[j], a);                                              \
-            bb = fma(Ny[i * NP + j], dn[j], bb);                                            \
+          _Pragma("unroll") for (int k = 0; k < NF; ++k) {                                  \
+            a = fma(Nx[i * NF + k], dn[k], a);                                              \
+            bb = fma(Ny[i * NF + k], dn[k], bb);                                            \
           }                                                                                 \
           ax[i] = a;                                                                        \
           ay[i] = bb;                                                                       \
@@ -356,10 +366,12 @@ __global__ void __launch_bounds__(256) k_mixed_div(const TS* __restrict__ q, con
                                                    const int4* __restrict__ elem,
                                                    const uint8_t* __restrict__ meta, int64_t E,
                                                    const double* __restrict__ MD,
-                                                   const double* __restrict__ MN, int mode,
+                                                   const double* __restrict__ MN,
+                                                   const int* __restrict__ MNcol, int mode,
                                                    double cb, double cg, int R, int epw,
                                                    int64_t nblocks, int remap,
                                                    const uint32_t* step, int stage_id) {
+  constexpr int NF = NP == 3 ? 2 : (NP == 6 ? 3 : 4);
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int r_raw = blockIdx.y * WAVE + lane;
@@ -412,18 +424,20 @@ __global__ void __launch_bounds__(256) k_mixed_div(const TS* __restrict__ q, con
           if (!((fm >> f) & 1)) continue;
           const int nb = f == 0 ? m.x : (f == 1 ? m.y : m.z);
           const int64_t qn = ((int64_t)nb * 2 * NP) * R + r;
+          const int* cf = MNcol + (o * 3 + f) * NF;
+          double fx[NF], fy[NF];
 #pragma unroll
-          for (int j = 0; j < NP; ++j) {
-            qx[j] = (double)q[qn + (int64_t)j * R];
-            qy[j] = (double)q[qn + (int64_t)(NP + j) * R];
+          for (int k = 0; k < NF; ++k) {
+            fx[k] = (double)q[qn + (int64_t)cf[k] * R];
+            fy[k] = (double)q[qn + (int64_t)(NP + cf[k]) * R];
           }
-          const double* Nx = MN + ((o * 3 + f) * 2 + 0) * NP * NP;
-          const double* Ny = MN + ((o * 3 + f) * 2 + 1) * NP * NP;
+          const double* Nx = MN + ((o * 3 + f) * 2 + 0) * NP * NF;
+          const double* Ny = MN + ((o * 3 + f) * 2 + 1) * NP * NF;
 #pragma unroll
           for (int i = 0; i < NP; ++i) {
             double a = acc[i];
 #pragma unroll
-            for (int j = 0; j < NP; ++j) a = fma(Nx[i * NP + j], qx[j], fma(Ny[i * NP + j], qy[j], a));
+            for (int k = 0; k < NF; ++k) a = fma(Nx[i * NF + k], fx[k], fma(Ny[i * NF + k], fy[k], a));
             acc[i] = a;
           }
         }
@@ -1179,27 +1193,29 @@ void launch_step_bump(uint32_t* step, hipStream_t st) {
 template <typename T, int NP>
 void mixed_stage_t(const void* us, const void* ub, void* out, void* q, const int4* elem,
                    const uint8_t* meta, int64_t E, const void* MG, const void* MD, const void* MN,
-                   int mode, double cb, double cg, int R, const Shape& sh, const uint32_t* step,
+                   const int* MNcol, int mode, double cb, double cg, int R, const Shape& sh, const uint32_t* step,
                    int stage_id, hipStream_t st) {
   const unsigned chunks = (unsigned)((R + 63) / 64);
   const dim3 grid((unsigned)sh.grid, chunks), block(64 * sh.waves);
   hipLaunchKernelGGL((k_mixed_grad<T, NP>), grid, block, 0, st, (const T*)us, (T*)q, elem, meta, E,
-                     (const double*)MG, (const double*)MN, R, sh.epw, sh.blocks, sh.remap ? 1 : 0);
+                     (const double*)MG, (const double*)MN, MNcol, R, sh.epw, sh.blocks,
+                     sh.remap ? 1 : 0);
   hipLaunchKernelGGL((k_mixed_div<T, NP>), grid, block, 0, st, (const T*)q, (const T*)us,
                      (const T*)ub, (T*)out, elem, meta, E, (const double*)MD, (const double*)MN,
-                     mode, cb, cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0, step, stage_id);
+                     MNcol, mode, cb, cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0, step, stage_id);
 }
 
 void launch_mixed_stage(int prec, int np, const void* us, const void* ub, void* out, void* q,
                         const int4* elem, const uint8_t* meta, int64_t E, const void* MG,
-                        const void* MD, const void* MN, int mode, double cb, double cg, int R,
-                        const Shape& sh, hipStream_t st, const uint32_t* step, int stage_id) {
+                        const void* MD, const void* MN, const int* MNcol, int mode, double cb,
+                        double cg, int R, const Shape& sh, hipStream_t st, const uint32_t* step,
+                        int stage_id) {
   if (prec == 0) {
-    DGD_DISPATCH_NP(np, mixed_stage_t<double, NP>(us, ub, out, q, elem, meta, E, MG, MD, MN, mode,
-                                                  cb, cg, R, sh, step, stage_id, st));
+    DGD_DISPATCH_NP(np, mixed_stage_t<double, NP>(us, ub, out, q, elem, meta, E, MG, MD, MN, MNcol,
+                                                  mode, cb, cg, R, sh, step, stage_id, st));
   } else {
-    DGD_DISPATCH_NP(np, mixed_stage_t<float, NP>(us, ub, out, q, elem, meta, E, MG, MD, MN, mode,
-                                                 cb, cg, R, sh, step, stage_id, st));
+    DGD_DISPATCH_NP(np, mixed_stage_t<float, NP>(us, ub, out, q, elem, meta, E, MG, MD, MN, MNcol,
+                                                 mode, cb, cg, R, sh, step, stage_id, st));
   }
 }
 

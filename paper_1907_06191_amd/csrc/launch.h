@@ -98,12 +98,13 @@ void launch_ic_project(int prec, int np, const int4* elem, int64_t E, const doub
 // state type), then the divergence pass with the stage combine of
 // launch_stage (modes 0 and 1).  meta [E]: face mask of the q-flux | 8 for
 // an extracellular element.  MG, MD: FP64 [2][8][2][np][np]; MN: FP64
-// [2][3][2][np][np].
+// [2][3][2][np][p+1], the neighbour blocks on the face-node columns MNcol
+// (int32 [2][3][p+1]).
 void launch_mixed_stage(int prec, int np, const void* us, const void* ub, void* out, void* q,
                         const int4* elem, const uint8_t* meta, int64_t E, const void* MG,
-                        const void* MD, const void* MN, int mode, double cb, double cg, int R,
-                        const Shape& sh, hipStream_t st, const uint32_t* step = nullptr,
-                        int stage_id = 0);
+                        const void* MD, const void* MN, const int* MNcol, int mode, double cb,
+                        double cg, int R, const Shape& sh, hipStream_t st,
+                        const uint32_t* step = nullptr, int stage_id = 0);
 
 // Point-mass initial data: u[(pe[k] np + i) R + col[k]] = vals[k np + i]
 // for k < n (the rest of u is cleared by the caller).

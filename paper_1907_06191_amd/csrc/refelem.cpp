@@ -233,6 +233,8 @@ RefElem build_ref_elem(int p, double eta) {
   R.MG.assign(2 * 8 * 2 * np * np, 0);
   R.MD.assign(2 * 8 * 2 * np * np, 0);
   R.MN.assign(2 * 3 * 2 * np * np, 0);
+  R.MNc.assign(2 * 3 * 2 * np * (p + 1), 0);
+  R.MNcol.assign(2 * 3 * (p + 1), 0);
   std::vector<double> v(np), vx(np), vy(np), w2(np), wx(np), wy(np);
   for (int o = 0; o < 2; ++o) {
     std::vector<double> M(np * np, 0), K(np * np, 0), GX(np * np, 0), GY(np * np, 0);
@@ -282,6 +284,23 @@ RefElem build_ref_elem(int p, double eta) {
           }
       }
     }
+    // the neighbour's nodes on each shared face (its cell-local positions
+    // shifted into this cell lie on the segment P0 -> P1)
+    for (int f = 0; f < 3; ++f) {
+      const double ex = P1[o][f][0] - P0[o][f][0], ey = P1[o][f][1] - P0[o][f][1];
+      int k = 0;
+      for (int j = 0; j < np; ++j) {
+        const double x = R.nodes[((1 - o) * np + j) * 2] + OFF[o][f][0] - P0[o][f][0];
+        const double y = R.nodes[((1 - o) * np + j) * 2 + 1] + OFF[o][f][1] - P0[o][f][1];
+        const double cross = ex * y - ey * x;
+        const double t = (ex * x + ey * y) / (ex * ex + ey * ey);
+        if (std::fabs(cross) < 1e-12 && t > -1e-12 && t < 1 + 1e-12) {
+          if (k > p) throw std::runtime_error("face node count");
+          R.MNcol[((size_t)o * 3 + f) * (p + 1) + k++] = j;
+        }
+      }
+      if (k != p + 1) throw std::runtime_error("face node count");
+    }
     // mixed form
     auto mi_times = [&](const std::vector<double>& A, double* dst) {
       for (int i = 0; i < np; ++i)
@@ -315,6 +334,25 @@ RefElem build_ref_elem(int p, double eta) {
         mi_times(Tn, &R.MN[(((size_t)o * 3 + f) * 2 + c) * np * np]);
       }
     }
+    for (int f = 0; f < 3; ++f)
+      for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < np; ++i)
+          for (int k = 0; k <= p; ++k)
+            R.MNc[((((size_t)o * 3 + f) * 2 + c) * np + i) * (p + 1) + k] =
+                R.MN[((((size_t)o * 3 + f) * 2 + c) * np + i) * np + R.MNcol[((size_t)o * 3 + f) * (p + 1) + k]];
+    // the columns left out vanish up to the rounding of the quadrature
+    double big = 0, off = 0;
+    for (int f = 0; f < 3; ++f)
+      for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < np; ++i)
+          for (int j = 0; j < np; ++j) {
+            const double v = std::fabs(R.MN[((((size_t)o * 3 + f) * 2 + c) * np + i) * np + j]);
+            bool kept = false;
+            for (int k = 0; k <= p; ++k) kept |= R.MNcol[((size_t)o * 3 + f) * (p + 1) + k] == j;
+            big = std::max(big, v);
+            if (!kept) off = std::max(off, v);
+          }
+    if (off > 1e-12 * big) throw std::runtime_error("neighbour block has weight off the face nodes");
     for (int mask = 0; mask < 8; ++mask) {
       std::vector<double> T = K;
       for (int f = 0; f < 3; ++f)

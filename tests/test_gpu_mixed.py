@@ -199,6 +199,29 @@ def test_mixed_checkpoint_resume_bitwise(dgd):
     b.close()
 
 
+def test_mixed_tuned_shape_same_bits(dgd):
+    """The autotuned launch shape of the two passes gives the same state,
+    bit for bit, as the default shape (each element's arithmetic does not
+    depend on which wave runs it)."""
+    g, pts = _case(5, 24, 51)
+    mesh = dgd.Mesh(g.L, g.N, np.zeros((0, 3)))
+    op = dgd.MixedOperator(mesh, g.disks, 2, 2.0, dgd.DGD_FP32, dt_max_ms=1e-4)
+    nval = mesh.info()["n_active"] * 6 * 5
+    states = []
+    for tuned in (1, 0):
+        dgd.dgd_set_option("autotune", tuned)
+        try:
+            run = dgd.Run(op, pts, 0.3)
+            shape = dgd.dgd_run_kernel(run.handle)[1]
+            run.advance(60, 1e-4)
+            states.append(dgd.dgd_run_get_state(run.handle, nval, np.float32))
+            run.close()
+        finally:
+            dgd.dgd_set_option("autotune", 1)
+        say(f"mixed shape (autotune={tuned}): {shape}")
+    assert np.array_equal(states[0], states[1])
+
+
 def test_mixed_errors(dgd):
     g, pts = _case(2, 16, 31)
     mesh = dgd.Mesh(g.L, g.N, np.zeros((0, 3)))
