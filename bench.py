@@ -43,11 +43,13 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes (FETCH_SIZE calibrated x 2.000, WRITE_SIZE x 1.000 by a
 # plain 1 GiB copy), keyed by (workload, kernel, sha256 prefix of
-# csrc/kernels.hip when the counters were taken).  A kernel source that
-# has changed since reports traffic null.  Summaries: profiles/.
+# csrc/kernels.hip when the counters were taken, launch shape as elements
+# per wave, waves, XCD order, workgroups): a changed kernel source or
+# another tuned shape reports traffic null.  Summaries: profiles/.
 MEASURED_TRAFFIC = {
-    ("pack512-p2", "k_stage<float,6>", "c15d21da22cb7b63"): 1141.9e6,
-    ("pack256-p3", "k_stage<float,10>", "c15d21da22cb7b63"): 833.6e6,
+    ("pack512-p2", "k_stage<float,6>", "875dfb92028a33ff", (4, 2, 0, 26674)): 1193.5e6,
+    ("pack512-p2", "k_stage<float,6>", "875dfb92028a33ff", (2, 4, 0, 26674)): 1141.7e6,
+    ("pack256-p3", "k_stage<float,10>", "875dfb92028a33ff", (4, 1, 1, 11968)): 795.6e6,
 }
 
 
@@ -167,18 +169,18 @@ def plain(args):
         "active_triangles": info["n_active"], "dof_per_rhs": info["n_active"] * npn, "rhs": R,
         "p": p, "dt_ms": dt, "lambda_max_per_ms": lam, "steps_full_solve": nsteps,
         "deltas_ms": [round(x, 4) for x in c["deltas"]]})
-    out["stage_shape_table"] = dgd.dgd_tune_export().strip().split("\n")
     out["sigma_solves_per_s"] = round(R / solve_s, 6)
     out["sigma_solves_note"] = ("RK3 path, projected: measured ms/step x the full Delta-landing "
                                 "schedule + measured moment reduction per Delta")
     out["mass_after_timed"] = float(np.abs(mom[:, 0] - 1).max())
-    traffic = MEASURED_TRAFFIC.get((args.workload, kernel, kernel_source_tag()))
+    shape_key = (shape["epw"], shape["waves"], shape["xcd_remap"], shape["grid"])
+    traffic = MEASURED_TRAFFIC.get((args.workload, kernel, kernel_source_tag(), shape_key))
     out["roofline"] = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
         "bytes_per_launch": bytes_per_launch, "launch_ms": round(launch_ms, 5), "launch_shape": shape,
         "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated), "
-                        "null unless measured on this kernel source"}
+                        "null unless measured on this kernel source and launch shape"}
     run.close()
     if args.expm:
         torch.cuda.synchronize()
@@ -194,6 +196,7 @@ def plain(args):
     if args.mixed:
         out["mixed_form"] = mixed_leg(args, dgd, g, pts, p, c, prec, R, out["sigma_solves_per_s"],
                                       info["n_active"])
+    out["stage_shape_table"] = dgd.dgd_tune_export().strip().split("\n")
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
