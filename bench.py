@@ -243,7 +243,8 @@ def mixed_leg(args, dgd, g, pts, p, c, prec, R, primal_sigma_per_s, n_ext):
            "mass_after_timed": float(np.abs(mom[:, 0] - 1).max()),
            "kernels": "k_mixed_grad + k_mixed_div per RK stage (axon elements skipped)",
            "note": "projected like the primal figure (ms/step x Delta-landing schedule); a different "
-                   "discretisation of the same problem, checked against its own oracle"}
+                   "discretisation of the same problem, checked against its own oracle; its Sigma "
+                   "differs from the primal form's by up to 2.4% at this h (Delta = 1 ms)"}
     op.close()
     return out
 
