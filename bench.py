@@ -181,6 +181,14 @@ def plain(args):
         "bytes_per_launch": bytes_per_launch, "launch_ms": round(launch_ms, 5), "launch_shape": shape,
         "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated), "
                         "null unless measured on this kernel source and launch shape"}
+    if kind == "mfma":
+        # useful flops of the contraction: the 10 x 40 stencil matrix times
+        # the 40 gathered values, per element and right-hand side
+        flops = 2.0 * 10 * 40 * info["n_active"] * R
+        out["roofline_mfma"] = {"bound": "mfma", "achieved": round(flops / (launch_ms * 1e-3) / 1e12, 3),
+                                "peak": 157.3, "unit": "TFLOP/s",
+                                "frac": round(flops / (launch_ms * 1e-3) / 1e12 / 157.3, 4),
+                                "flops_per_launch": flops, "dtype": "fp32 MFMA (v_mfma_f32_16x16x4_f32)"}
     run.close()
     if args.expm:
         torch.cuda.synchronize()
@@ -308,6 +316,8 @@ def main():
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
                     help="skip the mixed-form leg (the paper's own formulation on all pixels)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--p3-mfma", type=int, default=2, choices=[0, 1, 2],
+                    help="P3 FP32 stage kernel: 0 VALU, 1 matrix cores, 2 the faster (tuned)")
     ap.add_argument("--tune-file", default=None,
                     help="stage launch-shape table: merged in before the runs if the file "
                          "exists, written back after them (a run with a warm file does no tuning)")
@@ -321,6 +331,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     from paper_1907_06191_amd import dgd
+    dgd.dgd_set_option("p3_mfma", args.p3_mfma)
     if args.tune_file and os.path.exists(args.tune_file):
         with open(args.tune_file) as f:
             dgd.dgd_tune_import(f.read())
