@@ -47,9 +47,8 @@ HBM_PEAK_GBS = 8000.0
 # per wave, waves, XCD order, workgroups): a changed kernel source or
 # another tuned shape reports traffic null.  Summaries: profiles/.
 MEASURED_TRAFFIC = {
-    ("pack512-p2", "k_stage<float,6>", "875dfb92028a33ff", (4, 2, 0, 26674)): 1193.5e6,
-    ("pack512-p2", "k_stage<float,6>", "875dfb92028a33ff", (2, 4, 0, 26674)): 1141.7e6,
-    ("pack256-p3", "k_stage<float,10>", "875dfb92028a33ff", (4, 1, 1, 11968)): 795.6e6,
+    ("pack512-p2", "k_stage<float,6>", "d6925cca614e49fd", (2, 4, 0, 26674)): 1145.2e6,
+    ("pack256-p3", "k_stage<float,10>", "d6925cca614e49fd", (4, 2, 1, 4096)): 835.9e6,
 }
 
 

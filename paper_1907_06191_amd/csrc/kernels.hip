@@ -128,7 +128,12 @@ __device__ __forceinline__ void store_state(double* p, int64_t i, double v, uint
 //
 // mode 2 (Chebyshev recurrence of exp(t L), see launch_cheb):
 //   out = 2 (us + cg L(us)) - ub,  res += ck * out.
-template <typename TS, int NP>
+// MODE is the runtime mode fixed at compile time.  With SPLIT the presence
+// of the base state (BASE) and of absorbing box blocks (ABS) is fixed too;
+// without it both are tested at run time.  Which instantiation is faster
+// depends on the register allocation: P3 gains from SPLIT, P1 and P2 lose
+// (measured on gfx950), so the launcher splits for np = 10 only.
+template <typename TS, int NP, int MODE, bool SPLIT, bool BASE, bool ABS>
 __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const TS* ub, TS* out,
                                                const int4* __restrict__ elem, int64_t E,
                                                const double* __restrict__ S,
@@ -144,8 +149,9 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
   const int r_raw = blockIdx.y * WAVE + lane;
   const bool live = r_raw < R;
   const int r = live ? r_raw : R - 1;
-  const bool use_base = ub != nullptr;
-  const uint32_t smix = step_mix(step, stage_id);
+  const bool use_base = SPLIT ? BASE : ub != nullptr;
+  const bool absorb = SPLIT ? ABS : Bm != nullptr;
+  const uint32_t smix = MODE == 1 ? step_mix(step, stage_id) : 0u;
   const BlockIter it = block_iter(nblocks, remap);
   for (int64_t b = it.first; b < it.end; b += it.stride) {
     const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
@@ -205,7 +211,7 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
 #undef DGD_FACE
       // faces on the absorbing box (neighbour code -2; faces 0 and 1 only):
       // the outside value is zero, so the term acts on u itself
-      if (Bm != nullptr && (m.x == -2 || m.y == -2)) {
+      if (absorb && (m.x == -2 || m.y == -2)) {
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
           if ((f == 0 ? m.x : m.y) != -2) continue;
@@ -220,28 +226,30 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
         }
       }
       if (!live) continue;
-      if (mode == 0) {
+      if constexpr (MODE == 0) {
 #pragma unroll
         for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)(cg * acc[i]);
-      } else if (mode == 2) {
+      } else if constexpr (MODE == 2) {
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
           const double t = 2.0 * ((double)su[i] + cg * acc[i]) - (double)sb[i];
           out[self + (int64_t)i * R] = (TS)t;
           res[self + (int64_t)i * R] = (TS)((double)res[self + (int64_t)i * R] + ck * t);
         }
-      } else if (use_base) {
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-          const double b0 = (double)sb[i];
-          store_state(out, self + (int64_t)i * R, b0 + cb * ((double)su[i] - b0) + cg * acc[i],
-                      state_salt(m.w, i * R + r, smix));
-        }
       } else {
+        if (use_base) {
 #pragma unroll
-        for (int i = 0; i < NP; ++i)
-          store_state(out, self + (int64_t)i * R, (double)su[i] + cg * acc[i],
-                      state_salt(m.w, i * R + r, smix));
+          for (int i = 0; i < NP; ++i) {
+            const double b0 = (double)sb[i];
+            store_state(out, self + (int64_t)i * R, b0 + cb * ((double)su[i] - b0) + cg * acc[i],
+                        state_salt(m.w, i * R + r, smix));
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < NP; ++i)
+            store_state(out, self + (int64_t)i * R, (double)su[i] + cg * acc[i],
+                        state_salt(m.w, i * R + r, smix));
+        }
       }
     }
   }
@@ -1124,10 +1132,24 @@ void stage_t(const void* us, const void* ub, void* out, const int4* elem, int64_
              const void* N, int mode, double cb, double cg, int R, const Shape& sh,
              const uint32_t* step, int stage_id, const void* B, hipStream_t st) {
   const unsigned chunks = (unsigned)((R + 63) / 64);
-  hipLaunchKernelGGL((k_stage<T, NP>), dim3((unsigned)sh.grid, chunks), dim3(64 * sh.waves), 0, st,
-                     (const T*)us, (const T*)ub, (T*)out, elem, E, (const double*)S,
-                     (const double*)N, mode, cb, cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0, step,
-                     stage_id, (const double*)B);
+  const dim3 grid((unsigned)sh.grid, chunks), block(64 * sh.waves);
+#define DGD_STAGE_LAUNCH(MD, SP, BS, AB)                                                         \
+  hipLaunchKernelGGL((k_stage<T, NP, MD, SP, BS, AB>), grid, block, 0, st, (const T*)us,         \
+                     (const T*)ub, (T*)out, elem, E, (const double*)S, (const double*)N, mode, cb, \
+                     cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0, step, stage_id, (const double*)B)
+  const bool ab = B != nullptr;
+  if constexpr (NP == 10) {
+    if (mode == 0) {
+      if (ab) DGD_STAGE_LAUNCH(0, true, false, true); else DGD_STAGE_LAUNCH(0, true, false, false);
+    } else if (ub) {
+      if (ab) DGD_STAGE_LAUNCH(1, true, true, true); else DGD_STAGE_LAUNCH(1, true, true, false);
+    } else {
+      if (ab) DGD_STAGE_LAUNCH(1, true, false, true); else DGD_STAGE_LAUNCH(1, true, false, false);
+    }
+  } else {
+    if (mode == 0) DGD_STAGE_LAUNCH(0, false, false, false); else DGD_STAGE_LAUNCH(1, false, false, false);
+  }
+#undef DGD_STAGE_LAUNCH
 }
 
 // Advance a run's step counter (one lane, a vector store).
@@ -1267,11 +1289,19 @@ void launch_cheb(int np, const double* tcur, const double* tprev, double* tnext,
                  const int4* elem, int64_t E, const void* S, const void* N, double cg, double ck,
                  int R, const Shape& sh, hipStream_t st, const void* B) {
   const unsigned chunks = (unsigned)((R + 63) / 64);
-  DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage<double, NP>), dim3((unsigned)sh.grid, chunks),
-                                         dim3(64 * sh.waves), 0, st, tcur, tprev, tnext, elem, E,
-                                         (const double*)S, (const double*)N, 2, 0.0, cg, R, sh.epw,
-                                         sh.blocks, sh.remap ? 1 : 0, nullptr, 0, (const double*)B,
-                                         res, ck));
+  if (B) {
+    DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage<double, NP, 2, true, true, true>),
+                                           dim3((unsigned)sh.grid, chunks), dim3(64 * sh.waves), 0, st,
+                                           tcur, tprev, tnext, elem, E, (const double*)S,
+                                           (const double*)N, 2, 0.0, cg, R, sh.epw, sh.blocks,
+                                           sh.remap ? 1 : 0, nullptr, 0, (const double*)B, res, ck));
+  } else {
+    DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage<double, NP, 2, true, true, false>),
+                                           dim3((unsigned)sh.grid, chunks), dim3(64 * sh.waves), 0, st,
+                                           tcur, tprev, tnext, elem, E, (const double*)S,
+                                           (const double*)N, 2, 0.0, cg, R, sh.epw, sh.blocks,
+                                           sh.remap ? 1 : 0, nullptr, 0, (const double*)B, res, ck));
+  }
 }
 
 void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t st) {
