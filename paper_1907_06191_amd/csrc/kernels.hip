@@ -618,8 +618,9 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
 // skipped outright.  Waves whose elements mix the
 // two orientations (rare: meshes are ordered in orientation groups of four)
 // run once per orientation under a lane mask.  Modes and combine as in
-// k_stage (0 apply, 1 SSP-RK3 stage).
-template <typename TS, int NP, int G>
+// k_stage (0 apply, 1 SSP-RK3 stage).  ABS: the operator has absorbing box
+// blocks (Bm non-NULL); without them the box code is not compiled in.
+template <typename TS, int NP, int G, bool ABS>
 __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us, const TS* ub,
                                                       TS* out, const int4* __restrict__ elem,
                                                       int64_t E, const double* __restrict__ S,
@@ -655,8 +656,8 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
       const int o0 = __builtin_amdgcn_readfirstlane(o);
       const bool mixed = __ballot(o != o0) != 0;
       const bool partial = __ballot(mask != 7) != 0;
-      const bool box0 = Bm != nullptr && m.x == -2, box1 = Bm != nullptr && m.y == -2;
-      const bool any_box = __ballot(box0 || box1) != 0;
+      const bool box0 = ABS && m.x == -2, box1 = ABS && m.y == -2;
+      const bool any_box = ABS && __ballot(box0 || box1) != 0;
       // one element and right-hand side per lane with orientation oo (uniform)
       auto body = [&](const int oo) {
         const int64_t self = (e * NP) * (int64_t)R + r;
@@ -1257,12 +1258,14 @@ void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub
                          const int4* elem, int64_t E, const void* S, const void* F, const void* N,
                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st,
                          const uint32_t* step, int stage_id, const void* B) {
-#define DGD_PACKED_LAUNCH(T, GG)                                                                \
-  DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage_packed<T, NP, GG>), dim3((unsigned)sh.grid),  \
+#define DGD_PACKED_LAUNCH1(T, GG, AB)                                                           \
+  DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage_packed<T, NP, GG, AB>), dim3((unsigned)sh.grid), \
                                          dim3(64 * sh.waves), 0, st, (const T*)us, (const T*)ub, \
                                          (T*)out, elem, E, (const double*)S, (const double*)F,   \
                                          (const double*)N, mode, cb, cg, R, sh.epw, sh.blocks,   \
                                          sh.remap ? 1 : 0, step, stage_id, (const double*)B))
+#define DGD_PACKED_LAUNCH(T, GG)                                                                \
+  if (B) { DGD_PACKED_LAUNCH1(T, GG, true); } else { DGD_PACKED_LAUNCH1(T, GG, false); }
   if (prec == 0 && G == 4) {
     DGD_PACKED_LAUNCH(double, 4);
   } else if (prec == 0) {
@@ -1273,6 +1276,7 @@ void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub
     DGD_PACKED_LAUNCH(float, 2);
   }
 #undef DGD_PACKED_LAUNCH
+#undef DGD_PACKED_LAUNCH1
 }
 
 void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4* elem, int64_t E,
