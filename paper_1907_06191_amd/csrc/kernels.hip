@@ -620,7 +620,7 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
 // run once per orientation under a lane mask.  Modes and combine as in
 // k_stage (0 apply, 1 SSP-RK3 stage).  ABS: the operator has absorbing box
 // blocks (Bm non-NULL); without them the box code is not compiled in.
-template <typename TS, int NP, int G, bool ABS>
+template <typename TS, int NP, int G, bool ABS, int MODE>
 __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us, const TS* ub,
                                                       TS* out, const int4* __restrict__ elem,
                                                       int64_t E, const double* __restrict__ S,
@@ -638,7 +638,7 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
   const bool live_r = r_raw < R;
   const int r = live_r ? r_raw : R - 1;
   const bool use_base = ub != nullptr;
-  const uint32_t smix = step_mix(step, stage_id);
+  const uint32_t smix = MODE == 1 ? step_mix(step, stage_id) : 0u;
   const BlockIter it = block_iter(nblocks, remap);
   for (int64_t b = it.first; b < it.end; b += it.stride) {
     const int64_t q0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
@@ -736,7 +736,7 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
           }
         }
         if (!live) return;
-        if (mode == 0) {
+        if constexpr (MODE == 0) {
 #pragma unroll
           for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)(cg * acc[i]);
         } else if (use_base) {
@@ -1258,14 +1258,18 @@ void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub
                          const int4* elem, int64_t E, const void* S, const void* F, const void* N,
                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st,
                          const uint32_t* step, int stage_id, const void* B) {
-#define DGD_PACKED_LAUNCH1(T, GG, AB)                                                           \
-  DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage_packed<T, NP, GG, AB>), dim3((unsigned)sh.grid), \
+#define DGD_PACKED_LAUNCH1(T, GG, AB, MD)                                                       \
+  DGD_DISPATCH_NP(np, hipLaunchKernelGGL((k_stage_packed<T, NP, GG, AB, MD>), dim3((unsigned)sh.grid), \
                                          dim3(64 * sh.waves), 0, st, (const T*)us, (const T*)ub, \
                                          (T*)out, elem, E, (const double*)S, (const double*)F,   \
                                          (const double*)N, mode, cb, cg, R, sh.epw, sh.blocks,   \
                                          sh.remap ? 1 : 0, step, stage_id, (const double*)B))
 #define DGD_PACKED_LAUNCH(T, GG)                                                                \
-  if (B) { DGD_PACKED_LAUNCH1(T, GG, true); } else { DGD_PACKED_LAUNCH1(T, GG, false); }
+  if (mode == 0) {                                                                              \
+    if (B) { DGD_PACKED_LAUNCH1(T, GG, true, 0); } else { DGD_PACKED_LAUNCH1(T, GG, false, 0); } \
+  } else {                                                                                      \
+    if (B) { DGD_PACKED_LAUNCH1(T, GG, true, 1); } else { DGD_PACKED_LAUNCH1(T, GG, false, 1); } \
+  }
   if (prec == 0 && G == 4) {
     DGD_PACKED_LAUNCH(double, 4);
   } else if (prec == 0) {
