@@ -47,8 +47,8 @@ HBM_PEAK_GBS = 8000.0
 # per wave, waves, XCD order, workgroups): a changed kernel source or
 # another tuned shape reports traffic null.  Summaries: profiles/.
 MEASURED_TRAFFIC = {
-    ("pack512-p2", "k_stage<float,6>", "d6925cca614e49fd", (2, 4, 0, 26674)): 1145.2e6,
-    ("pack256-p3", "k_stage<float,10>", "d6925cca614e49fd", (4, 2, 1, 4096)): 835.9e6,
+    ("pack512-p2", "k_stage<float,6>", "9b24b7f978c80c07", (2, 4, 0, 26674)): 1144.4e6,
+    ("pack256-p3", "k_stage<float,10>", "9b24b7f978c80c07", (4, 2, 1, 5984)): 800.2e6,
 }
 
 
