@@ -67,36 +67,48 @@ __device__ inline BlockIter block_iter(int64_t nblocks, int remap) {
 // are that fraction: adding a uniform 29-bit integer r to the magnitude bits
 // and clearing those 29 bits carries into the kept part with probability
 // fraction / 2^29 (a carry into the exponent is the correct next binade),
-// and the result converts to FP32 exactly.  r hashes the kept bits with a
-// salt from the element's cell, orientation and face mask and the (node,
-// right-hand side) slot: independent of the fraction, deterministic, and
-// the same whether a geometry is solved alone or inside a batch.  Outside
+// and the result converts to FP32 exactly.  r comes from a hash of the
+// element's cell, orientation and face mask, the right-hand side, the step
+// and the stage (state_salt, once per element and right-hand side),
+// spread over the nodes by sr_node: independent of the value and of its
+// fraction, deterministic, and the same whether a geometry is solved alone
+// or inside a batch.  Outside
 // the FP32 normal range (zero, |v| < 2^-126 where an FP32 ulp is fixed, or
 // |v| >= 2^127) the value rounds to nearest.
-__device__ __forceinline__ float round_stochastic(double v, uint32_t salt) {
+__device__ __forceinline__ float round_stochastic(double v, uint32_t r) {
   const uint64_t b = (uint64_t)__double_as_longlong(v);
   const uint32_t hi = (uint32_t)(b >> 32);
   const uint32_t ex = (hi >> 20) & 0x7ffu;           // biased FP64 exponent
-  uint32_t r = hi ^ ((uint32_t)b >> 29) ^ salt;
-  r *= 0x9E3779B1u;
-  r ^= r >> 16;
-  r *= 0x85EBCA77u;
-  r ^= r >> 13;
   const uint64_t t = (b + (uint64_t)(r >> 3)) & ~0x1fffffffull;
   const float sr = (float)__longlong_as_double((long long)t);
   return ex - 897u <= 252u ? sr : (float)v;          // 2^-126 <= |v| < 2^127
 }
 
-// Salt of a stored value: the element's metadata and the (node,
-// right-hand side) slot, plus a mix of the run's step counter and the stage
-// within the step.  The counter makes the random threshold of a slot change
-// every step even when its value does not: with a threshold fixed per value,
-// a slot whose per-step increment stays below its threshold would never
-// move (the stagnation of rounding to nearest, for that share of slots),
-// which shows near equilibrium, where increments are a small fraction of an
-// ulp step after step.
-__device__ __forceinline__ uint32_t state_salt(int meta, int slot, uint32_t smix) {
-  return ((uint32_t)meta ^ ((uint32_t)slot * 0x85EBCA6Bu)) + smix;
+// Random bits of the stored values: a hash of the element's metadata, the
+// right-hand side and a mix of the run's step counter and the stage within
+// the step, then one cheap round per node.  The counter makes the random
+// threshold of a slot change every step even when its value does not: with
+// a fixed threshold, a slot whose per-step increment stays below it would
+// never move (the stagnation of rounding to nearest, for that share of
+// slots), which shows near equilibrium, where increments are a small
+// fraction of an ulp step after step.
+__device__ __forceinline__ uint32_t sr_mix(uint32_t x) {
+  x *= 0x9E3779B1u;
+  x ^= x >> 16;
+  x *= 0x85EBCA77u;
+  x ^= x >> 13;
+  return x;
+}
+// one hash per (element, right-hand side, step, stage) ...
+__device__ __forceinline__ uint32_t state_salt(int meta, int rhs, uint32_t smix) {
+  return sr_mix(((uint32_t)meta ^ ((uint32_t)rhs * 0x85EBCA6Bu)) + smix);
+}
+// ... and the bits of node `node` from it.
+__device__ __forceinline__ uint32_t sr_node(uint32_t h, int node) {
+  uint32_t x = h + (uint32_t)node * 0x9E3779B9u;
+  x *= 0x85EBCA77u;
+  x ^= x >> 13;
+  return x;
 }
 
 // Per-launch part of the salt; step is the run's device step counter
@@ -105,10 +117,10 @@ __device__ __forceinline__ uint32_t step_mix(const uint32_t* step, int stage_id)
   const uint32_t k = step ? step[0] : 0u;
   return (k * 3u + (uint32_t)stage_id) * 0x9E3779B9u;
 }
-__device__ __forceinline__ void store_state(float* p, int64_t i, double v, uint32_t salt) {
-  p[i] = round_stochastic(v, salt);
+__device__ __forceinline__ void store_state(float* p, int64_t i, double v, uint32_t h, int node) {
+  p[i] = round_stochastic(v, sr_node(h, node));
 }
-__device__ __forceinline__ void store_state(double* p, int64_t i, double v, uint32_t) { p[i] = v; }
+__device__ __forceinline__ void store_state(double* p, int64_t i, double v, uint32_t, int) { p[i] = v; }
 
 // mode 0 (operator apply):  out = cg * L(us)
 // mode 1 (SSP-RK3 stage):    out = base + cb * (us - base) + cg * L(us),
@@ -237,18 +249,19 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
           res[self + (int64_t)i * R] = (TS)((double)res[self + (int64_t)i * R] + ck * t);
         }
       } else {
+        const uint32_t hsr = state_salt(m.w, r, smix);
         if (use_base) {
 #pragma unroll
           for (int i = 0; i < NP; ++i) {
             const double b0 = (double)sb[i];
             store_state(out, self + (int64_t)i * R, b0 + cb * ((double)su[i] - b0) + cg * acc[i],
-                        state_salt(m.w, i * R + r, smix));
+                        hsr, i);
           }
         } else {
 #pragma unroll
           for (int i = 0; i < NP; ++i)
             store_state(out, self + (int64_t)i * R, (double)su[i] + cg * acc[i],
-                        state_salt(m.w, i * R + r, smix));
+                        hsr, i);
         }
       }
     }
@@ -451,6 +464,7 @@ __global__ void __launch_bounds__(256) k_mixed_div(const TS* __restrict__ q, con
         }
       }
       if (!live) continue;
+      const uint32_t hsr = state_salt(m.w, r, smix);
       if (mode == 0) {
 #pragma unroll
         for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)(cg * acc[i]);
@@ -460,13 +474,13 @@ __global__ void __launch_bounds__(256) k_mixed_div(const TS* __restrict__ q, con
           const double u = (double)us[self + (int64_t)i * R];
           const double b0 = (double)ub[self + (int64_t)i * R];
           store_state(out, self + (int64_t)i * R, b0 + cb * (u - b0) + cg * acc[i],
-                      state_salt(m.w, i * R + r, smix));
+                      hsr, i);
         }
       } else {
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
           const double u = (double)us[self + (int64_t)i * R];
-          store_state(out, self + (int64_t)i * R, u + cg * acc[i], state_salt(m.w, i * R + r, smix));
+          store_state(out, self + (int64_t)i * R, u + cg * acc[i], hsr, i);
         }
       }
     }
@@ -593,7 +607,7 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
           } else {
             const double uu = (double)u0[i][t], bb = (double)b0[i][t];
             r4[t] = round_stochastic(bb + cb * (uu - bb) + cg * val,
-                                     state_salt(m.w, row * R + (int)col + t, smix));
+                                     sr_node(state_salt(m.w, (int)col + t, smix), row));
           }
         }
         *(f32x4*)(out + idx) = r4;
@@ -736,6 +750,7 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
           }
         }
         if (!live) return;
+        const uint32_t hsr = state_salt(m.w, r, smix);
         if constexpr (MODE == 0) {
 #pragma unroll
           for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)(cg * acc[i]);
@@ -744,13 +759,13 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
           for (int i = 0; i < NP; ++i) {
             const double b0 = (double)sb[i];
             store_state(out, self + (int64_t)i * R, b0 + cb * ((double)su[i] - b0) + cg * acc[i],
-                        state_salt(m.w, i * R + r, smix));
+                        hsr, i);
           }
         } else {
 #pragma unroll
           for (int i = 0; i < NP; ++i)
             store_state(out, self + (int64_t)i * R, (double)su[i] + cg * acc[i],
-                        state_salt(m.w, i * R + r, smix));
+                        hsr, i);
         }
       };
       if (!mixed) {
