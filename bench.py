@@ -47,8 +47,8 @@ HBM_PEAK_GBS = 8000.0
 # per wave, waves, XCD order, workgroups): a changed kernel source or
 # another tuned shape reports traffic null.  Summaries: profiles/.
 MEASURED_TRAFFIC = {
-    ("pack512-p2", "k_stage<float,6>", "9b24b7f978c80c07", (2, 4, 0, 26674)): 1144.4e6,
-    ("pack256-p3", "k_stage<float,10>", "9b24b7f978c80c07", (4, 2, 1, 5984)): 800.2e6,
+    ("pack512-p2", "k_stage<float,6>", "280047a4b8896864", (2, 4, 0, 26674)): 1147.8e6,
+    ("pack256-p3", "k_stage<float,10>", "280047a4b8896864", (4, 2, 1, 5984)): 819.5e6,
 }
 
 
