@@ -372,3 +372,81 @@ def test_V13_chebyshev_matches_rk3_on_small_workload():
     b = osolve.solve(prob, pts, c["sigma0"], deltas, method="cheb")
     err = mom.rel_err(mom.sigma_a(a), mom.sigma_a(b))
     assert err.max() < 1e-9, err
+
+
+# ------------------------------------------------------ penalty size ----
+
+@pytest.mark.parametrize("outer", ["reflect", "absorb"])
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_penalty_magnitude_checkerboard(p, outer):
+    """Reading R2 fixes sigma_F = eta p^2 D / h with h the cell edge on all
+    three face types.  On a disk-free N x N mesh take u = +1 on every T0 and
+    -1 on every T1: grad u = 0, so only the penalty survives, and [u] = +-2
+    on every interior face: u^T A u = sigma * 4 * (total interior face
+    length) = 4 eta p^2 D (sqrt(2) N^2 + 2 N (N - 1)), with N^2 diagonals of
+    length sqrt(2) h and 2 N (N - 1) edges of length h.  With the absorbing
+    box each of the 4 N box faces adds sigma * h * 1^2.  u^T M u = N^2 h^2.
+    p instead of p^2, a missing D, the diagonal without its sqrt(2) length,
+    or h/sqrt(2) on the diagonal each move the quotient."""
+    N, L, D, eta = 5, 3.0, 1.7, 10.0
+    h = L / N
+    m = meshmod.build_mesh(L, N, NO_DISKS)
+    op = sipg.assemble(m, p, D, eta, outer=outer)
+    u = np.zeros((m.n_elements, op.Np))
+    u[:, 0] = np.where(m.orient == 0, 1.0, -1.0)      # constants in the monomial basis
+    u = u.ravel()
+    num = 4.0 * eta * p * p * D * (math.sqrt(2.0) * N * N + 2.0 * N * (N - 1))
+    if outer == "absorb":
+        num += 4.0 * N * eta * p * p * D
+    expect = num / (N * N * h * h)
+    got = (u @ (op.A @ u)) / (u @ (op.M @ u))
+    assert abs(got - expect) < 1e-12 * expect
+
+
+# ------------------------------------------------------------ mixture ----
+
+def test_mixture_hand_computed_two_points():
+    """Section 4.1's three covariance readings on a two-point case worked by
+    hand.  Point 1: M0 = 1, m1 = (1, 0), M2 = (2, 0, 1) -> Sigma_A = (2, 0, 1),
+    mu = (1, 0), Sigma_B = (1, 0, 1).  Point 2: M0 = 2, m1 = (0, 2),
+    M2 = (2, 2, 6) -> Sigma_A = (1, 1, 3), mu = (0, 1), Sigma_B = (1, 1, 2).
+    A = (1.5, 0.5, 2), B = (1, 0.5, 1.5), mubar = (0.5, 0.5),
+    C = A - mubar mubar^T = (1.25, 0.25, 1.75)."""
+    mom_ = np.array([[1.0, 1.0, 0.0, 2.0, 0.0, 1.0],
+                     [2.0, 0.0, 2.0, 2.0, 2.0, 6.0]])
+    r = mom.mixture(mom_)
+    assert np.allclose(r["A"], [1.5, 0.5, 2.0], rtol=0, atol=1e-15)
+    assert np.allclose(r["B"], [1.0, 0.5, 1.5], rtol=0, atol=1e-15)
+    assert np.allclose(r["C"], [1.25, 0.25, 1.75], rtol=0, atol=1e-15)
+
+
+def test_mixture_matches_pooled_sample_covariance():
+    """Brute force: each start point x_i carries a weighted point cloud y_ik
+    (weights w_ik, total mass M0_i).  Its moments about x_i feed ``mixture``;
+    the same readings follow from numpy's weighted covariance: B is the mean
+    of the per-point covariances, and C is the covariance of the pooled
+    displacements y_ik - x_i with weights w_ik / (m M0_i) (the equal-weight
+    mixture of the centred densities, about its own mean).  A swapped
+    cross-moment, a missing M0 normalisation or a mean taken before
+    centring fails it."""
+    rng = np.random.default_rng(7)
+    m, k = 5, 40
+    x0 = rng.uniform(0, 10, (m, 2))
+    moms, covs, pooled, pw = [], [], [], []
+    for i in range(m):
+        y = x0[i] + rng.normal(size=(k, 2)) * rng.uniform(0.5, 2.0, 2) + rng.uniform(-1, 1, 2)
+        w = rng.uniform(0.1, 1.0, k) * rng.uniform(0.5, 2.0)
+        d = y - x0[i]
+        M0 = w.sum()
+        moms.append([M0, (w * d[:, 0]).sum(), (w * d[:, 1]).sum(), (w * d[:, 0] ** 2).sum(),
+                     (w * d[:, 0] * d[:, 1]).sum(), (w * d[:, 1] ** 2).sum()])
+        covs.append(np.cov(d.T, aweights=w, bias=True))
+        pooled.append(d)
+        pw.append(w / (m * M0))
+    r = mom.mixture(np.array(moms))
+    B = np.mean(covs, axis=0)
+    C = np.cov(np.concatenate(pooled).T, aweights=np.concatenate(pw), bias=True)
+    sa = np.array([[mm[3] / mm[0], mm[4] / mm[0], mm[5] / mm[0]] for mm in moms]).mean(0)
+    assert np.allclose(r["A"], sa, rtol=1e-13)
+    assert np.allclose(r["B"], [B[0, 0], B[0, 1], B[1, 1]], rtol=1e-12, atol=1e-13)
+    assert np.allclose(r["C"], [C[0, 0], C[0, 1], C[1, 1]], rtol=1e-12, atol=1e-13)

@@ -13,10 +13,15 @@ produce seeded stand-ins:
   a disk that finds no place is dropped, and after ``max_fail_run``
   consecutive dropped disks the packing counts as jammed and placement
   stops.  Disks may cross the box edge.
-* ``start_points``: points uniform in the centred box of side ``box_frac*L``
-  (the paper draws its pulses in a centred 20 um box of a 50 um square,
-  section 4.2), rejected when closer than r + sqrt(2)*h to a disk centre, so
-  that the grid cell holding the point keeps its centroid outside every disk.
+* ``start_points``: points uniform over the extracellular part of the
+  centred box of side ``box_frac*L`` (section 4.1 draws the pulses uniformly
+  in the extracellular space; section 4.2 keeps them in a centred 20 um box
+  of a 50 um square).  On the pixel grid the extracellular space is the set
+  of cells whose centroid lies outside every disk, so a uniform proposal in
+  the box is kept iff the cell holding it is such a cell: the accepted
+  points are uniform over the kept cells' area, right up to the staircase
+  walls.  ``law="pore_interior"`` keeps the earlier, narrower law (points at
+  least r + sqrt(2) h from every disk centre) for comparison.
 
 All randomness comes from ``numpy.random.default_rng(seed)`` (PCG64).
 """
@@ -154,11 +159,32 @@ def coverage_fraction(disks: np.ndarray, L: float, samples: int = 1024) -> float
     return float(covered.mean())
 
 
+def _cell_kept(p: np.ndarray, disks: np.ndarray, L: float, N: int) -> np.ndarray:
+    """Whether the grid cell holding each point [k, 2] has its centroid
+    outside every disk (strict test, as the mesh builders read it; a point on
+    the far box edge belongs to the last cell)."""
+    h = L / N
+    ij = np.minimum(np.floor(p / h).astype(np.int64), N - 1)
+    c = (ij + 0.5) * h
+    if disks.shape[0] == 0:
+        return np.ones(p.shape[0], dtype=bool)
+    dx = c[:, 0, None] - disks[None, :, 0]
+    dy = c[:, 1, None] - disks[None, :, 1]
+    r = disks[None, :, 2]
+    return ~(dx * dx + dy * dy < r * r).any(axis=1)
+
+
 def start_points(disks: np.ndarray, L: float, N: int, m: int,
                  rng: np.random.Generator, box_frac: float = 0.4,
-                 center: tuple | None = None) -> np.ndarray:
-    """m start points uniform in the centred box of side box_frac*L, each at
-    least r + sqrt(2)*h from every disk centre (h = L/N).  float64 [m, 2]."""
+                 center: tuple | None = None, law: str = "extracellular") -> np.ndarray:
+    """m start points in the centred box of side box_frac*L, float64 [m, 2].
+
+    law = "extracellular" (default): uniform over the box area covered by
+    cells whose centroid is outside every disk (section 4.1).
+    law = "pore_interior": uniform in the box, each at least r + sqrt(2)*h
+    from every disk centre (a narrower law, kept for comparison)."""
+    if law not in ("extracellular", "pore_interior"):
+        raise ValueError("law must be 'extracellular' or 'pore_interior'")
     h = L / N
     cx0, cy0 = (0.5 * L, 0.5 * L) if center is None else center
     half = 0.5 * box_frac * L
@@ -171,7 +197,9 @@ def start_points(disks: np.ndarray, L: float, N: int, m: int,
         if guard > 100000:
             raise RuntimeError("could not place start points")
         p = rng.uniform(-half, half, size=(256, 2)) + np.array([cx0, cy0])
-        if disks.shape[0]:
+        if law == "extracellular":
+            ok = _cell_kept(p, disks, L, N)
+        elif disks.shape[0]:
             dx = p[:, 0, None] - disks[None, :, 0]
             dy = p[:, 1, None] - disks[None, :, 1]
             lim = disks[None, :, 2] + margin
