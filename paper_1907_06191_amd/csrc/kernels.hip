@@ -67,31 +67,31 @@ __device__ inline BlockIter block_iter(int64_t nblocks, int remap) {
 // are that fraction: adding a uniform 29-bit integer r to the magnitude bits
 // and clearing those 29 bits carries into the kept part with probability
 // fraction / 2^29 (a carry into the exponent is the correct next binade),
-// and the result converts to FP32 exactly.  r comes from a hash of the
-// element's cell, orientation and face mask, the right-hand side, the step
-// and the stage (state_salt, once per element and right-hand side),
-// spread over the nodes by sr_node: independent of the value and of its
-// fraction, deterministic, and the same whether a geometry is solved alone
-// or inside a batch.  Outside
-// the FP32 normal range (zero, |v| < 2^-126 where an FP32 ulp is fixed, or
-// |v| >= 2^127) the value rounds to nearest.
+// and the result converts to FP32 exactly.  Zero stays zero.  Below the
+// FP32 normal range (|v| < 2^-126 ~ 1.2e-38) the truncated value converts
+// with the hardware's rounding, an error below 2^-149 that no moment can
+// see; |v| >= 2^127 does not occur in a unit-mass state (and overflows to
+// infinity, which the mass check reports).
 __device__ __forceinline__ float round_stochastic(double v, uint32_t r) {
   const uint64_t b = (uint64_t)__double_as_longlong(v);
-  const uint32_t hi = (uint32_t)(b >> 32);
-  const uint32_t ex = (hi >> 20) & 0x7ffu;           // biased FP64 exponent
   const uint64_t t = (b + (uint64_t)(r >> 3)) & ~0x1fffffffull;
-  const float sr = (float)__longlong_as_double((long long)t);
-  return ex - 897u <= 252u ? sr : (float)v;          // 2^-126 <= |v| < 2^127
+  return (float)__longlong_as_double((long long)t);
 }
 
-// Random bits of the stored values: a hash of the element's metadata, the
-// right-hand side and a mix of the run's step counter and the stage within
-// the step, then one cheap round per node.  The counter makes the random
-// threshold of a slot change every step even when its value does not: with
-// a fixed threshold, a slot whose per-step increment stays below it would
-// never move (the stagnation of rounding to nearest, for that share of
-// slots), which shows near equilibrium, where increments are a small
-// fraction of an ulp step after step.
+// Random bits of the stored values.  A value's bits come from a hash of
+// (element, step and stage within the step) XOR a hash of its right-hand
+// side, rotated by an amount that depends on its node.  The element part
+// is wave-uniform in the one-element-per-wave kernels (scalar ALU work)
+// and the right-hand-side part is a constant of the lane, so a stored
+// value costs one rotate and one shift of random bits.  Every node's bits
+// are uniform and independent of the value they round, and for a fixed
+// right-hand side they change with the element and with every step: with
+// a threshold fixed in time, a slot whose per-step increment stays below
+// it would never move (the stagnation of rounding to nearest, for that
+// share of slots), which shows near equilibrium, where increments are a
+// small fraction of an ulp step after step.  Nothing depends on where an
+// element sits in memory, so a geometry gives the same bits alone or in a
+// batch.
 __device__ __forceinline__ uint32_t sr_mix(uint32_t x) {
   x *= 0x9E3779B1u;
   x ^= x >> 16;
@@ -99,16 +99,22 @@ __device__ __forceinline__ uint32_t sr_mix(uint32_t x) {
   x ^= x >> 13;
   return x;
 }
-// one hash per (element, right-hand side, step, stage) ...
-__device__ __forceinline__ uint32_t state_salt(int meta, int rhs, uint32_t smix) {
-  return sr_mix(((uint32_t)meta ^ ((uint32_t)rhs * 0x85EBCA6Bu)) + smix);
+// element part: the element's record word (cell, orientation, face mask)
+// and the step/stage mix
+__device__ __forceinline__ uint32_t elem_salt(int meta, uint32_t smix) {
+  return sr_mix((uint32_t)meta + smix);
 }
-// ... and the bits of node `node` from it.
+// right-hand-side part
+__device__ __forceinline__ uint32_t rhs_salt(int rhs) {
+  return sr_mix((uint32_t)rhs * 0x85EBCA6Bu ^ 0x6A09E667u);
+}
+__device__ __forceinline__ uint32_t state_salt(int meta, int rhs, uint32_t smix) {
+  return elem_salt(meta, smix) ^ rhs_salt(rhs);
+}
+// the bits of node `node` (node < 32): distinct rotations, so the nodes of
+// one element draw from different windows of the hash
 __device__ __forceinline__ uint32_t sr_node(uint32_t h, int node) {
-  uint32_t x = h + (uint32_t)node * 0x9E3779B9u;
-  x *= 0x85EBCA77u;
-  x ^= x >> 13;
-  return x;
+  return __builtin_rotateright32(h, (uint32_t)(node * 11) & 31u);
 }
 
 // Per-launch part of the salt; step is the run's device step counter
@@ -121,6 +127,40 @@ __device__ __forceinline__ void store_state(float* p, int64_t i, double v, uint3
   p[i] = round_stochastic(v, sr_node(h, node));
 }
 __device__ __forceinline__ void store_state(double* p, int64_t i, double v, uint32_t, int) { p[i] = v; }
+
+// Rows of state through a buffer resource based at p (raw addressing, no
+// range limit): a load or store names a lane offset (VGPR, fixed for the
+// kernel) and a wave-uniform byte offset (SGPR), so per-element address
+// arithmetic runs on the scalar unit and costs no vector instructions.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_at(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
+}
+__device__ __forceinline__ float buf_ld(float*, __amdgpu_buffer_rsrc_t rs, uint32_t voff,
+                                        uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+}
+__device__ __forceinline__ double buf_ld(double*, __amdgpu_buffer_rsrc_t rs, uint32_t voff,
+                                         uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ T ld_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  return buf_ld((T*)nullptr, rs, voff, soff);
+}
+__device__ __forceinline__ void st_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff,
+                                       float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, voff, soff, 0);
+}
+__device__ __forceinline__ void st_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff,
+                                       double v) {
+  typedef __attribute__((ext_vector_type(2))) unsigned int u32x2;
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, voff, soff, 0);
+}
+// a state value rounded for storage: FP32 stochastically, FP64 as is
+__device__ __forceinline__ float to_state(float*, double v, uint32_t h, int node) {
+  return round_stochastic(v, sr_node(h, node));
+}
+__device__ __forceinline__ double to_state(double*, double v, uint32_t, int) { return v; }
 
 // mode 0 (operator apply):  out = cg * L(us)
 // mode 1 (SSP-RK3 stage):    out = base + cb * (us - base) + cg * L(us),
@@ -161,9 +201,14 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
   const int r_raw = blockIdx.y * WAVE + lane;
   const bool live = r_raw < R;
   const int r = live ? r_raw : R - 1;
+  // the lane's byte offset within a node row, and the bytes per node row
+  const uint32_t voff = (uint32_t)r * (uint32_t)sizeof(TS);
+  const uint32_t row = (uint32_t)R * (uint32_t)sizeof(TS);
+  const int64_t elen = (int64_t)NP * R;     // values per element
   const bool use_base = SPLIT ? BASE : ub != nullptr;
   const bool absorb = SPLIT ? ABS : Bm != nullptr;
   const uint32_t smix = MODE == 1 ? step_mix(step, stage_id) : 0u;
+  const uint32_t hrhs = rhs_salt(r);
   const BlockIter it = block_iter(nblocks, remap);
   for (int64_t b = it.first; b < it.end; b += it.stride) {
     const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
@@ -172,37 +217,40 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
       const int4 m = elem[e];
       const int o = m.w & 1;
       const int mask = (m.w >> 1) & 7;
-      const int64_t self = (e * NP) * (int64_t)R + r;
       // issue every load of the element first: own nodes, the three
       // neighbours (a missing neighbour reads the element itself, a cache
       // hit, and its product is skipped below), the RK base state
-      const int64_t n0 = (m.x >= 0 ? (int64_t)m.x * NP * R + r : self);
-      const int64_t n1 = (m.y >= 0 ? (int64_t)m.y * NP * R + r : self);
-      const int64_t n2 = (m.z >= 0 ? (int64_t)m.z * NP * R + r : self);
+      const TS* pe = us + e * elen;
+      const __amdgpu_buffer_rsrc_t ru = rows_at(pe);
+      const __amdgpu_buffer_rsrc_t r0 = rows_at(m.x >= 0 ? us + (int64_t)m.x * elen : pe);
+      const __amdgpu_buffer_rsrc_t r1 = rows_at(m.y >= 0 ? us + (int64_t)m.y * elen : pe);
+      const __amdgpu_buffer_rsrc_t r2 = rows_at(m.z >= 0 ? us + (int64_t)m.z * elen : pe);
       TS su[NP], s0[NP], s1[NP], s2[NP], sb[NP];
 #pragma unroll
       for (int j = 0; j < NP; ++j) {
-        su[j] = us[self + (int64_t)j * R];
-        s0[j] = us[n0 + (int64_t)j * R];
-        s1[j] = us[n1 + (int64_t)j * R];
-        s2[j] = us[n2 + (int64_t)j * R];
+        su[j] = ld_row<TS>(ru, voff, j * row);
+        s0[j] = ld_row<TS>(r0, voff, j * row);
+        s1[j] = ld_row<TS>(r1, voff, j * row);
+        s2[j] = ld_row<TS>(r2, voff, j * row);
       }
       if (use_base) {
+        const __amdgpu_buffer_rsrc_t rb = rows_at(ub + e * elen);
 #pragma unroll
-        for (int j = 0; j < NP; ++j) sb[j] = ub[self + (int64_t)j * R];
+        for (int j = 0; j < NP; ++j) sb[j] = ld_row<TS>(rb, voff, j * row);
       }
       const double c = (double)su[0];
       double acc[NP];
       {
         const double* Se = S + (o * 8 + mask) * NP * NP;
         double d[NP];
+        d[0] = 0.0;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) d[j] = (double)su[j] - c;
+        for (int j = 1; j < NP; ++j) d[j] = (double)su[j] - c;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
           double a = 0.0;
 #pragma unroll
-          for (int j = 0; j < NP; ++j) a = fma(Se[i * NP + j], d[j], a);
+          for (int j = 1; j < NP; ++j) a = fma(Se[i * NP + j], d[j], a);
           acc[i] = a;
         }
       }
@@ -238,30 +286,32 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
         }
       }
       if (!live) continue;
+      const __amdgpu_buffer_rsrc_t ro = rows_at(out + e * elen);
       if constexpr (MODE == 0) {
 #pragma unroll
-        for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)(cg * acc[i]);
+        for (int i = 0; i < NP; ++i) st_row(ro, voff, i * row, (TS)(cg * acc[i]));
       } else if constexpr (MODE == 2) {
+        const __amdgpu_buffer_rsrc_t rr = rows_at(res + e * elen);
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
           const double t = 2.0 * ((double)su[i] + cg * acc[i]) - (double)sb[i];
-          out[self + (int64_t)i * R] = (TS)t;
-          res[self + (int64_t)i * R] = (TS)((double)res[self + (int64_t)i * R] + ck * t);
+          st_row(ro, voff, i * row, (TS)t);
+          st_row(rr, voff, i * row, (TS)((double)ld_row<TS>(rr, voff, i * row) + ck * t));
         }
       } else {
-        const uint32_t hsr = state_salt(m.w, r, smix);
+        const uint32_t hsr = elem_salt(m.w, smix) ^ hrhs;
         if (use_base) {
 #pragma unroll
           for (int i = 0; i < NP; ++i) {
             const double b0 = (double)sb[i];
-            store_state(out, self + (int64_t)i * R, b0 + cb * ((double)su[i] - b0) + cg * acc[i],
-                        hsr, i);
+            st_row(ro, voff, i * row,
+                   to_state((TS*)nullptr, b0 + cb * ((double)su[i] - b0) + cg * acc[i], hsr, i));
           }
         } else {
 #pragma unroll
           for (int i = 0; i < NP; ++i)
-            store_state(out, self + (int64_t)i * R, (double)su[i] + cg * acc[i],
-                        hsr, i);
+            st_row(ro, voff, i * row,
+                   to_state((TS*)nullptr, (double)su[i] + cg * acc[i], hsr, i));
         }
       }
     }
