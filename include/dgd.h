@@ -269,6 +269,30 @@ int dgd_eap_solve(dgd_op* op, const double* points, int32_t n_points, double sig
                   const double* deltas_ms, int32_t n_deltas, double* sigma_out,
                   double* moments_out, void* d_ws, size_t ws_bytes, void* hip_stream);
 
+/*
+ * dgd_eap_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same solve and outputs, with the run's buffers (three
+ * state buffers, start points, partial sums, step counter) in a fixed
+ * 64 MiB device array of the library instead of a workspace.  Each GPU the
+ * library runs on holds its own copy of that array until the process ends;
+ * its address is resolved on the first call on a device.  Makes no
+ * hipMalloc/hipFree or other allocating call: the stage launch shape is the
+ * tuned one if its key is already in the table (else the option default),
+ * steps launch eagerly (no graph), and hip_stream is used as given (NULL:
+ * the null stream).  The op's device must be current.
+ * Limits and errors: as dgd_eap_solve, plus EINVAL for sigma0_um == 0 (the
+ * point-mass upload allocates) or another device current, and ENOMEM when
+ * the run needs more than 64 MiB (3 E np R state bytes plus about
+ * R (16 + 48 E / 64) bytes).  Calls that overlap on one GPU share the
+ * array and race: serialise them (one host thread, or one stream).  The
+ * array keeps the last call's contents; everything a call reads is written
+ * by that call first.
+ */
+int dgd_eap_solve_noalloc(dgd_op* op, const double* points, int32_t n_points, double sigma0_um,
+                          const double* deltas_ms, int32_t n_deltas, double* sigma_out,
+                          double* moments_out, void* hip_stream);
+
 /* dgd_eap_solve with the q-space signal (dgd_run_signal) at every Delta:
  *   signal_out: host float64 [n_points][n_deltas][n_q][2];
  *   moments_out: NULL or host float64 [n_points][n_deltas][6] as in

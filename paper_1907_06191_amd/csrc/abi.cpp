@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -540,15 +542,21 @@ void init_point_mass(dgd_run* run) {
 
 // Allocate (or adopt) the workspace, copy the start points, and project
 // the initial pulse of every (geometry, start point) (sigma0 = 0: the
-// point mass).
+// point mass).  no_alloc: the caller's workspace and stream (NULL: the null
+// stream) are used as given, nothing is tuned and no step graph is captured,
+// so the run makes no device allocation; point-mass data (sigma0 = 0) are
+// refused (their upload allocates).
 dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, void* d_ws,
-                    size_t ws_bytes, void* hip_stream) {
+                    size_t ws_bytes, void* hip_stream, bool no_alloc = false) {
   size_t total, off[9];
   ws_layout(t, R, &total, off);
+  if (no_alloc && (!d_ws || sigma0 == 0))
+    fail(DGD_EINVAL, "internal: allocation-free run without a workspace or with a point mass");
   auto* run = new dgd_run();
   try {
     run->t = t;
     run->R = R;
+    run->eager = no_alloc;
     run->x0.assign(x0, x0 + (size_t)t.G * R * 2);
     if (d_ws) {
       if (ws_bytes < total) fail(DGD_ENOMEM, "workspace smaller than the size the library reports");
@@ -559,7 +567,7 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
       run->own_ws = true;
       run->ws_bytes = total;
     }
-    if (hip_stream) {
+    if (hip_stream || no_alloc) {
       run->stream = (hipStream_t)hip_stream;
     } else {
       DGD_HIP_CHECK(hipStreamCreateWithFlags(&run->stream, hipStreamNonBlocking));
@@ -589,7 +597,8 @@ dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, 
                                  hipMemcpyHostToDevice, run->stream));
     // the stage launch shape, tuned on first use of its key (the two stage
     // buffers are free until the first step)
-    if (g_opt.autotune) tune_target(run->t, R, run->U1, run->U2, run->U, run->stream, false);
+    if (g_opt.autotune && !no_alloc)
+      tune_target(run->t, R, run->U1, run->U2, run->U, run->stream, false);
     if (t.form == 1) {
       // the mixed-form stage kernels skip axon elements (u = 0 there): the
       // stage buffers start at zero (after the tuner used them as scratch)
@@ -668,7 +677,7 @@ void run_advance(dgd_run* run, int64_t n_steps, double dt) {
   if (n_steps == 0) return;
   const int64_t G = g_opt.graph_steps;
   int64_t left = n_steps;
-  if (g_opt.graphs && left >= G) {
+  if (g_opt.graphs && !run->eager && left >= G) {
     hipGraphExec_t ex = step_graph(run, G, dt);
     while (left >= G) {
       DGD_HIP_CHECK(hipGraphLaunch(ex, run->stream));
@@ -885,6 +894,50 @@ size_t batch_group_bytes(const dgd_batch::Group& grp, const dgd_batch* b, RunTar
   ws_layout(t, b->R, &total, off);
   if (t_out) *t_out = t;
   return total;
+}
+
+// Advance a plain run through the Delta list, writing Sigma_A [R][nd][3]
+// and (if non-NULL) the moments [R][nd][6]; stops at the first Delta whose
+// moments fail the mass check and reports it.
+void solve_deltas(dgd_run* run, const std::vector<std::pair<int64_t, double>>& sched, int n_points,
+                  int n_deltas, double* sigma_out, double* moments_out) {
+  std::vector<double> mom((size_t)n_points * 6);
+  std::string why;
+  for (int k = 0; k < n_deltas; ++k) {
+    run_advance(run, sched[k].first, sched[k].second);
+    const int mrc = run_moments(run, mom.data(), &why);
+    for (int r = 0; r < n_points; ++r) {
+      const double* m = &mom[(size_t)r * 6];
+      double* s = &sigma_out[((size_t)r * n_deltas + k) * 3];
+      s[0] = m[3] / m[0];
+      s[1] = m[4] / m[0];
+      s[2] = m[5] / m[0];
+      if (moments_out) std::memcpy(&moments_out[((size_t)r * n_deltas + k) * 6], m, 6 * sizeof(double));
+    }
+    if (mrc) fail(mrc, why);
+  }
+}
+
+// Device scratch of the allocation-free solve: a fixed array in the code
+// object, so each GPU the library runs on holds its own copy until the
+// process ends.  In host code `scratch` is only a host-side stand-in for
+// the symbol: each device's copy is resolved once, with that device
+// current, through hipGetSymbolAddress, and only that address is passed on.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+void* scratch_address(int device) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) return it->second;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    fail(DGD_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  addr[device] = p;
+  return p;
 }
 
 }  // namespace
@@ -1396,30 +1449,43 @@ int dgd_eap_solve(dgd_op* op, const double* points, int32_t n_points, double sig
   rc = dgd_run_create(op, points, n_points, sigma0_um, d_ws, ws_bytes, hip_stream, &run);
   if (rc) return rc;
   rc = guarded([&]() -> int {
-    std::vector<double> mom((size_t)n_points * 6);
-    int status = DGD_OK;
-    std::string why;
-    for (int k = 0; k < n_deltas; ++k) {
-      run_advance(run, sched[k].first, sched[k].second);
-      const int mrc = run_moments(run, mom.data(), &why);
-      for (int r = 0; r < n_points; ++r) {
-        const double* m = &mom[(size_t)r * 6];
-        double* s = &sigma_out[((size_t)r * n_deltas + k) * 3];
-        s[0] = m[3] / m[0];
-        s[1] = m[4] / m[0];
-        s[2] = m[5] / m[0];
-        if (moments_out)
-          std::memcpy(&moments_out[((size_t)r * n_deltas + k) * 6], m, 6 * sizeof(double));
-      }
-      if (mrc) {
-        status = mrc;
-        break;
-      }
-    }
-    if (status) fail(status, why);
+    solve_deltas(run, sched, n_points, n_deltas, sigma_out, moments_out);
     return DGD_OK;
   });
   dgd_run_destroy(run);
+  return rc;
+}
+
+int dgd_eap_solve_noalloc(dgd_op* op, const double* points, int32_t n_points, double sigma0_um,
+                          const double* deltas_ms, int32_t n_deltas, double* sigma_out,
+                          double* moments_out, void* hip_stream) {
+  dgd_run* run = nullptr;
+  const int rc = guarded([&]() -> int {
+    if (!op || !points || !deltas_ms || !sigma_out) fail(DGD_EINVAL, "NULL argument");
+    if (n_points < 1) fail(DGD_EINVAL, "n_points must be >= 1");
+    if (n_deltas < 1) fail(DGD_EINVAL, "n_deltas must be >= 1");
+    if (!(sigma0_um > 0) || !std::isfinite(sigma0_um))
+      fail(DGD_EINVAL, "the allocation-free solve needs sigma0 > 0 (point-mass data allocate)");
+    int dev = -1;
+    DGD_HIP_CHECK(hipGetDevice(&dev));
+    if (dev != op->mesh->device)
+      fail(DGD_EINVAL, "the current device is not the one the operator was built on");
+    const auto sched = schedule(deltas_ms, n_deltas, op->dt_nom);
+    const RunTarget t = plain_target(op);
+    size_t total, off[9];
+    ws_layout(t, n_points, &total, off);
+    if (total > kScratchBytes)
+      fail(DGD_ENOMEM, "the allocation-free solve needs " + std::to_string(total) +
+                           " bytes of device scratch; its limit is " +
+                           std::to_string(kScratchBytes) + " bytes (64 MiB)");
+    check_points(op->mesh->host, points, n_points);
+    check_axon_cells(op, points, n_points);
+    run = run_create(t, points, n_points, sigma0_um, scratch_address(dev), kScratchBytes,
+                     hip_stream, true);
+    solve_deltas(run, sched, n_points, n_deltas, sigma_out, moments_out);
+    return DGD_OK;
+  });
+  run_destroy(run);
   return rc;
 }
 

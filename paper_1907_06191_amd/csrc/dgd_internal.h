@@ -189,6 +189,7 @@ struct dgd_run {
   int* d_blk_start = nullptr; // [G + 1] (plain runs: {0, nblk_red})
   uint32_t* d_step = nullptr; // steps taken (salt of the stochastic rounding)
   int64_t steps = 0;
+  bool eager = false;         // never capture step graphs (allocation-free solve)
   dgd::Shape sh;              // stage launch shape
   int kind = 0;               // stage kernel (VALU, packed, matrix cores)
   std::vector<double> x0;

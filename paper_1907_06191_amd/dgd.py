@@ -112,6 +112,8 @@ _sig("dgd_eap_solve_expm", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, 
                             ctypes.c_double, _c_dp, _c_dp, ctypes.POINTER(ctypes.c_int64)])
 _sig("dgd_eap_solve", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, ctypes.c_int32, _c_dp,
                        _c_dp, _vp, ctypes.c_size_t, _vp])
+_sig("dgd_eap_solve_noalloc", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, ctypes.c_int32,
+                               _c_dp, _c_dp, _vp])
 _sig("dgd_autotune", [_vp, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_int32), _c_dp])
 _sig("dgd_run_signal", [_vp, _c_dp, ctypes.c_int32, _c_dp])
 _sig("dgd_eap_solve_signal", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp, ctypes.c_int32, _c_dp,
@@ -347,6 +349,19 @@ def dgd_eap_solve(op, points, sigma0: float, deltas, workspace=None, ws_bytes: i
         ws_bytes = workspace.numel() * workspace.element_size()
     _check(_lib.dgd_eap_solve(op, _ptr(pts), n, float(sigma0), _ptr(d), int(d.size), _ptr(sig), _ptr(mom),
                               _dev_ptr(workspace), int(ws_bytes), _stream_ptr(stream)))
+    return sig, mom
+
+
+def dgd_eap_solve_noalloc(op, points, sigma0: float, deltas, stream=None):
+    """dgd_eap_solve in the library's fixed device scratch (no allocation).
+    Returns (sigma [n][nDelta][3], moments [n][nDelta][6])."""
+    pts = _f64(points, (2,))
+    d = _f64(deltas).ravel()
+    n = pts.shape[0]
+    sig = np.zeros((n, d.size, 3))
+    mom = np.zeros((n, d.size, 6))
+    _check(_lib.dgd_eap_solve_noalloc(op, _ptr(pts), n, float(sigma0), _ptr(d), int(d.size), _ptr(sig),
+                                      _ptr(mom), _stream_ptr(stream)))
     return sig, mom
 
 
