@@ -106,6 +106,22 @@ def time_steps(advance, steps, stream):
     return ev0.elapsed_time(ev1)
 
 
+def copy_bandwidth(stream, nbytes=1 << 30, reps=10):
+    """A plain device-to-device copy of nbytes timed with HIP events:
+    (read + written bytes) / time, the bandwidth a streaming kernel reaches
+    on this machine (context for the 8 TB/s peak)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    with torch.cuda.stream(stream):
+        b.copy_(a)
+        ms = time_steps(lambda k: [b.copy_(a) for _ in range(k)], reps, stream)
+    del a, b
+    gbs = 2.0 * nbytes * reps / (ms * 1e-3) / 1e9
+    return {"gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "note": f"torch copy_ of {nbytes >> 20} MiB, {reps} repetitions, read + write bytes"}
+
+
 def base_record(args, value, ms_per_step, dtype, config):
     return {
         "metric": "DG GDoF-updates/s (and Sigma-solves/s) at 1e-4 rel err vs FP64 oracle",
@@ -204,6 +220,7 @@ def plain(args):
         out["mixed_form"] = mixed_leg(args, dgd, g, pts, p, c, prec, R, out["sigma_solves_per_s"],
                                       info["n_active"])
     out["stage_shape_table"] = dgd.dgd_tune_export().strip().split("\n")
+    out["hbm_copy"] = copy_bandwidth(stream)
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

@@ -132,29 +132,43 @@ __device__ __forceinline__ void store_state(double* p, int64_t i, double v, uint
 // range limit): a load or store names a lane offset (VGPR, fixed for the
 // kernel) and a wave-uniform byte offset (SGPR), so per-element address
 // arithmetic runs on the scalar unit and costs no vector instructions.
+// Cache policy of the state streams (gfx950 buffer instructions: bit 1 =
+// non-temporal).  The stage output and the RK base state are touched once
+// per launch, so they stream past the caches; the stage input stays
+// temporal (face neighbours read it again from L2).
+#ifndef DGD_CPOL_OUT
+#define DGD_CPOL_OUT 2
+#endif
+#ifndef DGD_CPOL_BASE
+#define DGD_CPOL_BASE 2
+#endif
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_at(const void* p) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
 }
+template <int CP>
 __device__ __forceinline__ float buf_ld(float*, __amdgpu_buffer_rsrc_t rs, uint32_t voff,
                                         uint32_t soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, CP));
 }
+template <int CP>
 __device__ __forceinline__ double buf_ld(double*, __amdgpu_buffer_rsrc_t rs, uint32_t voff,
                                          uint32_t soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, CP));
 }
-template <typename T>
+template <typename T, int CP = 0>
 __device__ __forceinline__ T ld_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
-  return buf_ld((T*)nullptr, rs, voff, soff);
+  return buf_ld<CP>((T*)nullptr, rs, voff, soff);
 }
+template <int CP = 0>
 __device__ __forceinline__ void st_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff,
                                        float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, voff, soff, CP);
 }
+template <int CP = 0>
 __device__ __forceinline__ void st_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff,
                                        double v) {
   typedef __attribute__((ext_vector_type(2))) unsigned int u32x2;
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, voff, soff, CP);
 }
 // a state value rounded for storage: FP32 stochastically, FP64 as is
 __device__ __forceinline__ float to_state(float*, double v, uint32_t h, int node) {
@@ -236,7 +250,7 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
       if (use_base) {
         const __amdgpu_buffer_rsrc_t rb = rows_at(ub + e * elen);
 #pragma unroll
-        for (int j = 0; j < NP; ++j) sb[j] = ld_row<TS>(rb, voff, j * row);
+        for (int j = 0; j < NP; ++j) sb[j] = ld_row<TS, DGD_CPOL_BASE>(rb, voff, j * row);
       }
       const double c = (double)su[0];
       double acc[NP];
@@ -304,13 +318,13 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
 #pragma unroll
           for (int i = 0; i < NP; ++i) {
             const double b0 = (double)sb[i];
-            st_row(ro, voff, i * row,
+            st_row<DGD_CPOL_OUT>(ro, voff, i * row,
                    to_state((TS*)nullptr, b0 + cb * ((double)su[i] - b0) + cg * acc[i], hsr, i));
           }
         } else {
 #pragma unroll
           for (int i = 0; i < NP; ++i)
-            st_row(ro, voff, i * row,
+            st_row<DGD_CPOL_OUT>(ro, voff, i * row,
                    to_state((TS*)nullptr, (double)su[i] + cg * acc[i], hsr, i));
         }
       }
