@@ -71,6 +71,24 @@ def schedule_steps(deltas, dt):
     return n
 
 
+def usable_cpus():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def host_workers():
+    """Worker processes for the oracle: every CPU this process may use, up to
+    the host's per-GPU share when the environment states one
+    (OMP_NUM_THREADS)."""
+    n = usable_cpus()
+    share = os.environ.get("OMP_NUM_THREADS")
+    if share and share.isdigit() and int(share) > 0:
+        n = min(n, int(share))
+    return max(1, n)
+
+
 def cpu_baseline(g, pts, p, D, eta, sigma0, dt, lam, budget_s=20.0):
     """The FP64 oracle's SSP-RK3 on the same mesh, on a bounded sample:
     a few start points (one per worker process) for a fixed number of steps."""
@@ -78,7 +96,7 @@ def cpu_baseline(g, pts, p, D, eta, sigma0, dt, lam, budget_s=20.0):
     t0 = time.time()
     prob = osolve.prepare(g.L, g.N, g.disks, p, D, eta, lam=lam)
     setup = time.time() - t0
-    workers = max(1, min(8, os.cpu_count() or 1))
+    workers = host_workers()
     sample = pts[:workers]
     t0 = time.time()
     osolve.solve(prob, sample[:1], sigma0, [3 * dt], method="rk3", dt_nom=dt, workers=1)
@@ -89,6 +107,7 @@ def cpu_baseline(g, pts, p, D, eta, sigma0, dt, lam, budget_s=20.0):
     el = time.time() - t0
     v = prob.op.ndof * sample.shape[0] * steps / el / 1e9
     return {"value": v, "unit": "GDoF-updates/s", "cores": workers, "kind": "oracle",
+            "host_cpu_count": os.cpu_count(), "host_cpus_usable": usable_cpus(),
             "sample": f"oracle SSP-RK3 (scipy CSR, FP64) on the same mesh: {sample.shape[0]} start "
                       f"points x {steps} steps, one worker process per start point, {el:.1f} s "
                       f"(+{setup:.1f} s assembly, not timed)"}

@@ -215,13 +215,20 @@ int dgd_run_create(dgd_op* op, const double* points, int32_t n_points, double si
 int dgd_run_advance(dgd_run* run, int64_t n_steps, double dt_ms);
 
 /* FP64 moments about each start point, host [n_points][6] =
- * (M0, mx, my, Mxx, Mxy, Myy).  Synchronises the run's stream.
+ * (M0, mx, my, Mxx, Mxy, Myy); n_doubles is the capacity of moments_out
+ * (EINVAL below 6 n_points).  Synchronises the run's stream.
  * Returns EUNSTABLE if a moment is not finite or |M0 - 1| > the
- * precision's tolerance (1e-9 FP64, 1e-3 otherwise; with an absorbing box
- * M0 outside [-tol, 1 + tol], tol 1e-6 FP64, 1e-3 otherwise, since the
+ * precision's tolerance (1e-9 FP64, 1e-5 otherwise; with an absorbing box
+ * M0 outside [-tol, 1 + tol], tol 1e-6 FP64, 1e-5 otherwise, since the
  * discrete solution's mass may exceed 1 by a discretisation error there);
  * moments_out is filled either way. */
-int dgd_run_moments(dgd_run* run, double* moments_out);
+int dgd_run_moments(dgd_run* run, double* moments_out, size_t n_doubles);
+
+/* Sizes of a run's host-side buffers: n_values = n_active * np * n_points
+ * state values of value_bytes bytes each (4 FP32, 8 FP64), and n_points.
+ * Each output may be NULL. */
+int dgd_run_shape(const dgd_run* run, int64_t* n_values, int32_t* n_points,
+                  int32_t* value_bytes);
 
 /* Narrow-pulse q-space signal of the propagator of each start point (the
  * propagator of section 1; its Fourier transform is the diffusion-weighted
@@ -235,12 +242,14 @@ int dgd_run_moments(dgd_run* run, double* moments_out);
 int dgd_run_signal(dgd_run* run, const double* q, int32_t n_q, double* signal_out);
 
 /* Copy the state to or from the host (checkpoint / resume); host buffer of
- * n_active * np * n_points values of the op's state type.  Synchronous.
+ * n_active * np * n_points values of the op's state type (dgd_run_shape),
+ * layout [element][node][start point]; bytes is the buffer's size: EINVAL
+ * when it is smaller (get) or differs (set).  Synchronous.
  * A checkpoint is the state and the step count: FP32 stores round
  * stochastically with the step count in the salt, so a resumed run repeats
  * the uninterrupted one bit for bit when its step count is restored too. */
-int dgd_run_get_state(dgd_run* run, void* host_out);
-int dgd_run_set_state(dgd_run* run, const void* host_in);
+int dgd_run_get_state(dgd_run* run, void* host_out, size_t bytes);
+int dgd_run_set_state(dgd_run* run, const void* host_in, size_t bytes);
 /* Steps taken by the run (since creation or the last set). */
 int dgd_run_step_count(const dgd_run* run, int64_t* steps_out);
 int dgd_run_set_step_count(dgd_run* run, int64_t steps);
@@ -342,8 +351,11 @@ int dgd_batch_groups(const dgd_batch* batch, int32_t* n_groups, int32_t* group_p
                      int32_t* group_size, double* group_dt, int64_t* group_dof);
 /* Advance one group by n_steps SSP-RK3 steps of dt_ms. */
 int dgd_batch_advance(dgd_batch* batch, int32_t group, int64_t n_steps, double dt_ms);
-/* FP64 moments, host [n_geoms][n_points][6]; EUNSTABLE as dgd_run_moments. */
-int dgd_batch_moments(dgd_batch* batch, double* moments_out);
+/* FP64 moments, host [n_geoms][n_points][6] (n_doubles: capacity, EINVAL
+ * below 6 n_geoms n_points); EUNSTABLE as dgd_run_moments. */
+int dgd_batch_moments(dgd_batch* batch, double* moments_out, size_t n_doubles);
+/* Geometries and start points per geometry of a batch (outputs nullable). */
+int dgd_batch_shape(const dgd_batch* batch, int32_t* n_geoms, int32_t* n_points);
 void dgd_batch_destroy(dgd_batch* batch);
 
 /* Whole batched solve through the Delta list (landing schedule per group);

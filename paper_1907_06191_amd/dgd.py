@@ -82,9 +82,11 @@ _sig("dgd_operator_destroy", [_vp], None)
 _sig("dgd_run_create", [_vp, _c_dp, ctypes.c_int32, ctypes.c_double, _vp, ctypes.c_size_t, _vp,
                         ctypes.POINTER(_vp)])
 _sig("dgd_run_advance", [_vp, ctypes.c_int64, ctypes.c_double])
-_sig("dgd_run_moments", [_vp, _c_dp])
-_sig("dgd_run_get_state", [_vp, _vp])
-_sig("dgd_run_set_state", [_vp, _vp])
+_sig("dgd_run_moments", [_vp, _c_dp, ctypes.c_size_t])
+_sig("dgd_run_shape", [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                       ctypes.POINTER(ctypes.c_int32)])
+_sig("dgd_run_get_state", [_vp, _vp, ctypes.c_size_t])
+_sig("dgd_run_set_state", [_vp, _vp, ctypes.c_size_t])
 _sig("dgd_run_kernel", [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)])
 _sig("dgd_run_step_count", [_vp, ctypes.POINTER(ctypes.c_int64)])
 _sig("dgd_run_set_step_count", [_vp, ctypes.c_int64])
@@ -94,7 +96,8 @@ _sig("dgd_batch_create", [_vp, ctypes.c_int32, _c_dp, ctypes.c_int32, ctypes.c_d
                           _vp, ctypes.POINTER(_vp)])
 _sig("dgd_batch_groups", [_vp, ctypes.POINTER(ctypes.c_int32), _vp, _vp, _vp, _vp])
 _sig("dgd_batch_advance", [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_double])
-_sig("dgd_batch_moments", [_vp, _c_dp])
+_sig("dgd_batch_moments", [_vp, _c_dp, ctypes.c_size_t])
+_sig("dgd_batch_shape", [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)])
 _sig("dgd_batch_destroy", [_vp], None)
 _sig("dgd_eap_solve_batch", [_vp, ctypes.c_int32, _c_dp, ctypes.c_int32, ctypes.c_double, _c_dp,
                              ctypes.c_int32, _c_dp, _c_dp, _vp, ctypes.c_size_t, _vp])
@@ -294,23 +297,49 @@ def dgd_run_advance(run, n_steps: int, dt_ms: float) -> None:
     _check(_lib.dgd_run_advance(run, int(n_steps), float(dt_ms)))
 
 
-def dgd_run_moments(run, n_points: int, check: bool = True) -> np.ndarray:
-    out = np.zeros((n_points, 6))
-    rc = _lib.dgd_run_moments(run, _ptr(out))
+def dgd_run_shape(run):
+    """(state values, start points, bytes per state value) of a run."""
+    nv, npt, vb = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.dgd_run_shape(run, ctypes.byref(nv), ctypes.byref(npt), ctypes.byref(vb)))
+    return nv.value, npt.value, vb.value
+
+
+def dgd_run_moments(run, n_points: int = None, check: bool = True) -> np.ndarray:
+    """Moments [n_points][6]; the buffer is sized from the run itself."""
+    npt = dgd_run_shape(run)[1]
+    if n_points is not None and n_points != npt:
+        raise ValueError(f"run has {npt} start points, not {n_points}")
+    out = np.zeros((npt, 6))
+    rc = _lib.dgd_run_moments(run, _ptr(out), out.size)
     if check:
         _check(rc)
     return out
 
 
-def dgd_run_get_state(run, n_values: int, dtype) -> np.ndarray:
-    out = np.zeros(n_values, dtype=dtype)
-    _check(_lib.dgd_run_get_state(run, out.ctypes.data))
+def _state_dtype(vb):
+    return np.float64 if vb == 8 else np.float32
+
+
+def dgd_run_get_state(run, n_values: int = None, dtype=None) -> np.ndarray:
+    """The run's state as a flat array of its own type and length."""
+    nv, _, vb = dgd_run_shape(run)
+    dt = _state_dtype(vb)
+    if n_values is not None and n_values != nv:
+        raise ValueError(f"run holds {nv} state values, not {n_values}")
+    if dtype is not None and np.dtype(dtype) != np.dtype(dt):
+        raise ValueError(f"run state is {np.dtype(dt)}, not {np.dtype(dtype)}")
+    out = np.zeros(nv, dtype=dt)
+    _check(_lib.dgd_run_get_state(run, out.ctypes.data, out.nbytes))
     return out
 
 
 def dgd_run_set_state(run, state: np.ndarray) -> None:
+    nv, _, vb = dgd_run_shape(run)
+    dt = _state_dtype(vb)
     s = np.ascontiguousarray(state)
-    _check(_lib.dgd_run_set_state(run, s.ctypes.data))
+    if s.dtype != np.dtype(dt) or s.size != nv:
+        raise ValueError(f"run holds {nv} values of {np.dtype(dt)}; got {s.size} of {s.dtype}")
+    _check(_lib.dgd_run_set_state(run, s.ctypes.data, s.nbytes))
 
 
 def dgd_run_step_count(run) -> int:
@@ -511,9 +540,20 @@ def dgd_batch_advance(batch, group: int, n_steps: int, dt_ms: float) -> None:
     _check(_lib.dgd_batch_advance(batch, int(group), int(n_steps), float(dt_ms)))
 
 
-def dgd_batch_moments(batch, n_geoms: int, n_points: int, check: bool = True) -> np.ndarray:
-    out = np.zeros((n_geoms, n_points, 6))
-    rc = _lib.dgd_batch_moments(batch, _ptr(out))
+def dgd_batch_shape(batch):
+    """(geometries, start points per geometry) of a batch."""
+    g, n = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.dgd_batch_shape(batch, ctypes.byref(g), ctypes.byref(n)))
+    return g.value, n.value
+
+
+def dgd_batch_moments(batch, n_geoms: int = None, n_points: int = None, check: bool = True) -> np.ndarray:
+    """Moments [n_geoms][n_points][6]; the buffer is sized from the batch itself."""
+    g, n = dgd_batch_shape(batch)
+    if (n_geoms is not None and n_geoms != g) or (n_points is not None and n_points != n):
+        raise ValueError(f"batch has {g} geometries x {n} start points")
+    out = np.zeros((g, n, 6))
+    rc = _lib.dgd_batch_moments(batch, _ptr(out), out.size)
     if check:
         _check(rc)
     return out

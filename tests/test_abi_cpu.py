@@ -153,3 +153,30 @@ def test_tuning_table_text_round_trip():
     assert dgd.dgd_tune_export() == ""
     assert dgd._lib.dgd_tune_import(None) == dgd.DGD_EINVAL
     dgd.dgd_set_option("autotune", 1)
+
+
+def test_host_code_under_address_and_ub_sanitizers(tmp_path):
+    """The host-only parts of the library (mesh builder, reference element
+    and quadrature, launch-shape table parser) built with g++ and
+    -fsanitize=address,undefined and driven over ordinary and edge-case
+    inputs by tests/host_sanitize.cpp: any invalid access, leak or undefined
+    operation aborts the run."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("g++ or the ROCm headers are missing")
+    csrc = os.path.join(ROOT, "paper_1907_06191_amd", "csrc")
+    exe = str(tmp_path / "host_sanitize")
+    cmd = [gxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+           "-fno-sanitize-recover=all", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           os.path.join(ROOT, "tests", "host_sanitize.cpp"), os.path.join(csrc, "mesh_host.cpp"),
+           os.path.join(csrc, "refelem.cpp"), os.path.join(csrc, "tune.cpp"),
+           "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-o", exe]
+    b = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert b.returncode == 0, b.stderr[-4000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
+    assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
+    assert "host checks passed" in r.stdout

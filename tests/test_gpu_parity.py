@@ -181,6 +181,22 @@ def test_determinism_graphs_and_checkpoint(dgd):
     d, sd = run([64], restore=s137)
     assert np.array_equal(sd[0], sa[0])
     assert np.array_equal(d[-1], a[-1])
+    # host buffers are sized from the run: a wrong count or type is refused
+    # by the binding, and the C entry points check the byte count themselves
+    import ctypes
+    r = dgd.Run(op, pts, 0.3)
+    with pytest.raises(ValueError):
+        dgd.dgd_run_get_state(r.handle, nval + 1, np.float32)
+    with pytest.raises(ValueError):
+        dgd.dgd_run_set_state(r.handle, np.zeros(nval, np.float64))
+    short = np.zeros(nval - 1, np.float32)
+    assert dgd._lib.dgd_run_get_state(r.handle, short.ctypes.data, short.nbytes) == dgd.DGD_EINVAL
+    assert dgd._lib.dgd_run_set_state(r.handle, short.ctypes.data, short.nbytes) == dgd.DGD_EINVAL
+    m = np.zeros(4 * 6 - 1)
+    assert dgd._lib.dgd_run_moments(r.handle, m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    m.size) == dgd.DGD_EINVAL
+    assert dgd.dgd_run_shape(r.handle) == (nval, 4, 4)
+    r.close()
 
 
 def test_auto_dt_is_stable(dgd):
