@@ -127,6 +127,14 @@ __device__ __forceinline__ void store_state(float* p, int64_t i, double v, uint3
   p[i] = round_stochastic(v, sr_node(h, node));
 }
 __device__ __forceinline__ void store_state(double* p, int64_t i, double v, uint32_t, int) { p[i] = v; }
+// the same with a non-temporal store (a stage output is not read again
+// within the launch)
+__device__ __forceinline__ void store_state_nt(float* p, int64_t i, double v, uint32_t h, int node) {
+  __builtin_nontemporal_store(round_stochastic(v, sr_node(h, node)), p + i);
+}
+__device__ __forceinline__ void store_state_nt(double* p, int64_t i, double v, uint32_t, int) {
+  __builtin_nontemporal_store(v, p + i);
+}
 
 // Rows of state through a buffer resource based at p (raw addressing, no
 // range limit): a load or store names a lane offset (VGPR, fixed for the
@@ -752,7 +760,7 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
         }
         if (use_base) {
 #pragma unroll
-          for (int j = 0; j < NP; ++j) sb[j] = ub[self + (int64_t)j * R];
+          for (int j = 0; j < NP; ++j) sb[j] = __builtin_nontemporal_load(ub + self + (int64_t)j * R);
         }
         const double c = (double)su[0];
         double d[NP];
@@ -822,13 +830,13 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
 #pragma unroll
           for (int i = 0; i < NP; ++i) {
             const double b0 = (double)sb[i];
-            store_state(out, self + (int64_t)i * R, b0 + cb * ((double)su[i] - b0) + cg * acc[i],
+            store_state_nt(out, self + (int64_t)i * R, b0 + cb * ((double)su[i] - b0) + cg * acc[i],
                         hsr, i);
           }
         } else {
 #pragma unroll
           for (int i = 0; i < NP; ++i)
-            store_state(out, self + (int64_t)i * R, (double)su[i] + cg * acc[i],
+            store_state_nt(out, self + (int64_t)i * R, (double)su[i] + cg * acc[i],
                         hsr, i);
         }
       };

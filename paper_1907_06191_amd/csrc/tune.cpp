@@ -87,28 +87,28 @@ TuneParams tune_stage(const std::string& key, int64_t units, int prec, int64_t n
     launch_fill_random_f32((float*)a, n, 0x5eedull, st);
   DGD_HIP_CHECK(hipGetLastError());
   if (!base) base = a;
-  // Launches alternate between a and b (stage input -> output), each also
-  // reading `base`: the common stage shape (stages 2 and 3 of SSP-RK3).
-  int flip = 0;
-  auto launch = [&](const Shape& sh) {
-    const void* src = flip ? b : a;
-    void* dst = flip ? a : b;
-    flip ^= 1;
-    launch_one(sh, src, base, dst);
+  // One timed unit is an SSP-RK3 step's pattern of launches: a stage
+  // without a base state (a -> b), then two stages reading `base`
+  // (b -> a, a -> b), so the tuned shape is the fastest for the mix of
+  // kernels a step runs, not for one of them.
+  auto step = [&](const Shape& sh) {
+    launch_one(sh, a, nullptr, b);
+    launch_one(sh, b, base, a);
+    launch_one(sh, a, base, b);
   };
   Events ev;
+  // ms per launch over `reps` steps, after one untimed step
   auto time_ms = [&](const TuneParams& p, int reps) {
     const Shape sh = tune_shape(p, units);
-    launch(sh);
-    launch(sh);
+    step(sh);
     DGD_HIP_CHECK(hipEventRecord(ev.a, st));
-    for (int i = 0; i < reps; ++i) launch(sh);
+    for (int i = 0; i < reps; ++i) step(sh);
     DGD_HIP_CHECK(hipEventRecord(ev.b, st));
     DGD_HIP_CHECK(hipEventSynchronize(ev.b));
     DGD_HIP_CHECK(hipGetLastError());
     float ms = 0;
     DGD_HIP_CHECK(hipEventElapsedTime(&ms, ev.a, ev.b));
-    return (double)ms / reps;
+    return (double)ms / (3.0 * reps);
   };
 
   std::vector<TuneParams> cand;
@@ -125,23 +125,31 @@ TuneParams tune_stage(const std::string& key, int64_t units, int prec, int64_t n
         }
   }
   // Warm the device up (clocks ramp up under load: a cold start would
-  // favour whatever is timed last) for about 30 ms, then time every
-  // candidate for about 2 ms twice, in forward and in reverse order, keep
-  // the better time, and time the best four again with three times the
-  // launches.
-  double est = time_ms(TuneParams(), 3);
+  // favour whatever is timed last) for about 30 ms; time every candidate
+  // for about 3 ms twice, in forward and in reverse order, keeping the
+  // better time; then time the best six again in three interleaved rounds
+  // of about 10 ms each and keep each one's best.
+  double est = time_ms(TuneParams(), 1);
   for (double spent = 0; spent < 30.0;) {
-    const int n = std::max(3, std::min(200, (int)std::ceil(10.0 / std::max(est, 1e-3))));
+    const int n = std::max(1, std::min(100, (int)std::ceil(10.0 / std::max(3.0 * est, 1e-3))));
     est = time_ms(TuneParams(), n);
-    spent += std::max(est, 1e-3) * (n + 2);
+    spent += std::max(3.0 * est, 1e-3) * (n + 1);
   }
-  const int reps = std::max(3, std::min(200, (int)std::ceil(2.0 / std::max(est, 1e-3))));
+  auto reps_for = [&](double ms_target) {
+    return std::max(1, std::min(300, (int)std::ceil(ms_target / std::max(3.0 * est, 1e-3))));
+  };
+  const int reps = reps_for(3.0);
   for (auto& p : cand) p.ms = time_ms(p, reps);
   for (auto it = cand.rbegin(); it != cand.rend(); ++it) it->ms = std::min(it->ms, time_ms(*it, reps));
   std::sort(cand.begin(), cand.end(),
             [](const TuneParams& x, const TuneParams& y) { return x.ms < y.ms; });
-  const size_t top = std::min<size_t>(4, cand.size());
-  for (size_t i = 0; i < top; ++i) cand[i].ms = std::min(cand[i].ms, time_ms(cand[i], 3 * reps));
+  const size_t top = std::min<size_t>(6, cand.size());
+  const int reps_fine = reps_for(10.0);
+  for (int round = 0; round < 3; ++round)
+    for (size_t i = 0; i < top; ++i) {
+      const double t = time_ms(cand[i], reps_fine);
+      cand[i].ms = round == 0 ? t : std::min(cand[i].ms, t);
+    }
   std::sort(cand.begin(), cand.begin() + top,
             [](const TuneParams& x, const TuneParams& y) { return x.ms < y.ms; });
   const TuneParams best = cand[0];

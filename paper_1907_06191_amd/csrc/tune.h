@@ -34,11 +34,12 @@ Shape tune_shape(const TuneParams& p, int64_t units);
 // One launch of the kernel being tuned: out = stage(src, base).
 using StageLaunch = std::function<void(const Shape&, const void* src, const void* base, void* out)>;
 
-// Time every candidate shape of `launch` over `units` work units, using a
-// and b (n_values states of the given precision each) as scratch and
-// reading `base` (n_values finite states, left unchanged; NULL: a is filled
-// and read as the base).  Stores the fastest under `key` and returns it.
-// Synchronises the stream.
+// Time every candidate shape of `launch` over `units` work units on an
+// SSP-RK3 step's pattern of launches (one stage without a base state, two
+// reading `base`), using a and b (n_values states of the given precision
+// each) as scratch and reading `base` (n_values finite states, left
+// unchanged; NULL: a is filled and read as the base).  Stores the fastest
+// under `key` and returns it (ms per launch).  Synchronises the stream.
 TuneParams tune_stage(const std::string& key, int64_t units, int prec, int64_t n_values, void* a,
                       void* b, const void* base, const StageLaunch& launch, hipStream_t st);
 
