@@ -433,6 +433,12 @@ void dgd_surrogate_destroy(dgd_surrogate* s);
  *                  T1 per cell), so that aligned runs share an orientation
  *   "packed"       1 (default) = runs with at most 32 right-hand sides use the
  *                  packed stage kernel (4 or 2 elements per wave)
+ *   "sort_classes" 1 = packed runs (plain and batched, created afterwards)
+ *                  step an element table grouped by class (orientation,
+ *                  face mask) within windows of 512 elements and padded per
+ *                  class run, so that each wave holds one face mask;
+ *                  0 (default) = mesh order.  Host state buffers keep the
+ *                  mesh order either way
  *   "autotune"     1 (default) = runs take the tuned stage launch shape of
  *                  their key, tuning it when the run is created if the key
  *                  is new; 0 = the shape options above

@@ -46,6 +46,7 @@ struct Options {
   bool packed = true;       // R <= 32: several elements per wave (packed stage kernel)
   int p3_mfma = 2;          // P3 FP32 stages on matrix cores: 0 never, 1 always, 2 when faster
   bool autotune = true;     // tune the stage launch shape per key on first use
+  int sort_classes = 0;     // packed runs on class-sorted element tables: 0 never, 1 always
 };
 Options g_opt;
 
@@ -107,12 +108,66 @@ void* upload(const std::vector<T>& v) {
   return d;
 }
 
-// The element table goes to the device on first use (operator build), so
+// Element table of a mesh in the order the packed stage kernel (G
+// elements per wave, G > 1) runs it, in plain and batched runs alike: the
+// elements of each window of kSortWindow consecutive mesh elements are
+// grouped by class (orientation and face mask: the low four bits of the
+// record) and every class run is padded with inert elements of its class
+// to a multiple of G, so that each wave sees one face mask and skips the
+// terms of absent faces.  Windows keep face neighbours close in memory.
+// Neighbour indices are local to the member; index[e] is the position of
+// mesh element e.  G = 1 keeps the mesh order.
+constexpr int64_t kSortWindow = 512;
+
+void member_table(const dgd_mesh* m, int G, std::vector<int4>* tab, std::vector<int64_t>* index) {
+  const std::vector<int4>& src = m->packed;
+  const int64_t E = (int64_t)src.size();
+  tab->clear();
+  index->assign(E, -1);
+  if (G <= 1) {
+    tab->assign(src.begin(), src.end());
+    for (int64_t e = 0; e < E; ++e) (*index)[e] = e;
+    return;
+  }
+  tab->reserve(E + E / 8);
+  std::vector<int64_t> bucket[16];
+  for (int64_t w0 = 0; w0 < E; w0 += kSortWindow) {
+    const int64_t w1 = std::min(E, w0 + kSortWindow);
+    for (auto& v : bucket) v.clear();
+    for (int64_t e = w0; e < w1; ++e) bucket[src[e].w & 15].push_back(e);
+    for (int cls = 0; cls < 16; ++cls) {
+      for (int64_t e : bucket[cls]) {
+        (*index)[e] = (int64_t)tab->size();
+        tab->push_back(src[e]);
+      }
+      int4 pad;
+      pad.x = pad.y = pad.z = -1;
+      pad.w = (int)((uint32_t)cls | ((uint32_t)kPadCell << 4) | ((uint32_t)kPadCell << 18));
+      while (bucket[cls].size() % G) {
+        tab->push_back(pad);
+        bucket[cls].push_back(-1);
+      }
+    }
+  }
+  for (int4& c : *tab) {
+    if (c.x >= 0) c.x = (int)(*index)[c.x];
+    if (c.y >= 0) c.y = (int)(*index)[c.y];
+    if (c.z >= 0) c.z = (int)(*index)[c.z];
+  }
+}
+
+// The element tables go to the device on first use (operator build), so
 // that meshes can be built and inspected on a host without a GPU.
 void ensure_mesh_on_device(const dgd_mesh* cm) {
   dgd_mesh* m = const_cast<dgd_mesh*>(cm);
   if (m->d_elem) return;
   DGD_HIP_CHECK(hipGetDevice(&m->device));
+  for (int k = 0; k < 2; ++k) {
+    dgd_mesh::Order& o = m->order[k];
+    o.index.assign(1, {});
+    member_table(m, k ? 4 : 2, &o.table, &o.index[0]);
+    o.d_elem = (int4*)upload(o.table);
+  }
   m->d_elem = (int4*)upload(m->packed);
 }
 
@@ -170,6 +225,21 @@ StageKind valu_kind(const RunTarget& t, int R) {
 }
 
 int packed_group(int R) { return R <= 16 ? 4 : 2; }
+
+// The target a plain run of R right-hand sides steps: the class-sorted
+// element table when the packed stage kernel runs it, else the mesh order.
+// Host buffers of the state stay in mesh order (dgd_run_get_state).
+RunTarget run_target(const dgd_op* op, int R) {
+  RunTarget t = plain_target(op);
+  if (valu_kind(t, R) != kPacked || !g_opt.sort_classes) return t;
+  const dgd_mesh::Order& o = op->mesh->order[packed_group(R) == 4 ? 1 : 0];
+  if (!o.d_elem) fail(DGD_EINVAL, "internal: sorted element table missing");
+  t.elem = o.d_elem;
+  t.E = (int64_t)o.table.size();
+  t.nblk_red = reduce_shape(t.E).blocks;
+  t.member_index = &o.index;
+  return t;
+}
 
 // Work units a stage launch shape counts: elements, or element groups of
 // the packed kernel.
@@ -507,7 +577,8 @@ void init_point_mass(dgd_run* run) {
     for (int64_t e = 0; e < m.n_elements(); ++e) {
       auto it = want.find(((int64_t)m.cj[e] * m.N + m.ci[e]) * 2 + m.orient[e]);
       if (it == want.end()) continue;
-      for (int r : it->second) pe[(size_t)g * R + r] = t.hosts[g].second + e;
+      const int64_t at = t.member_index ? (*t.member_index)[g][e] : t.hosts[g].second + e;
+      for (int r : it->second) pe[(size_t)g * R + r] = at;
     }
     for (int r = 0; r < R; ++r) {
       const size_t k = (size_t)g * R + r;
@@ -880,11 +951,20 @@ void batch_plan(dgd_batch* b) {
 
 // Target and workspace bytes of a group: its geometries' element tables
 // concatenated, each padded to whole reduction blocks.
+// Elements per wave the group's stage kernel packs (1: one per wave).
+int batch_pack(const RunTarget& t, int R) {
+  return valu_kind(t, R) == kPacked && g_opt.sort_classes ? packed_group(R) : 1;
+}
+
 size_t batch_group_bytes(const dgd_batch::Group& grp, const dgd_batch* b, RunTarget* t_out) {
   RunTarget t = plain_target(b->ops[grp.geoms[0]]);
+  const int Gp = batch_pack(t, b->R);
   int64_t E = 0;
+  std::vector<int4> tab;
+  std::vector<int64_t> index;
   for (int g : grp.geoms) {
-    const int64_t Eg = b->ops[g]->mesh->host.n_elements();
+    member_table(b->ops[g]->mesh, Gp, &tab, &index);
+    const int64_t Eg = (int64_t)tab.size();
     E += (Eg + kReducePer - 1) / kReducePer * kReducePer;
   }
   t.E = E;
@@ -981,6 +1061,9 @@ int dgd_set_option(const char* name, int64_t value) {
       g_opt.mesh_group = (int)value;
     } else if (n == "packed") {
       g_opt.packed = value != 0;
+    } else if (n == "sort_classes") {
+      if (value < 0 || value > 1) fail(DGD_EINVAL, "sort_classes must be 0 or 1");
+      g_opt.sort_classes = (int)value;
     } else if (n == "autotune") {
       g_opt.autotune = value != 0;
     } else fail(DGD_EINVAL, "unknown option " + n);
@@ -997,7 +1080,7 @@ int dgd_autotune(dgd_op* op, int32_t n_points, void* hip_stream, int32_t* shape_
   int rc = guarded([&]() -> int {
     if (!op) fail(DGD_EINVAL, "op is NULL");
     if (n_points < 1) fail(DGD_EINVAL, "n_points must be >= 1");
-    RunTarget t = plain_target(op);
+    RunTarget t = run_target(op, n_points);
     const size_t bytes = (size_t)t.E * t.np * n_points * state_bytes(t.prec);
     DGD_HIP_CHECK(hipMalloc(&a, bytes));
     DGD_HIP_CHECK(hipMalloc(&b, bytes));
@@ -1141,6 +1224,8 @@ int dgd_mesh_occupancy(const dgd_mesh* mesh, int32_t size, uint8_t* image_out) {
 void dgd_mesh_destroy(dgd_mesh* mesh) {
   if (!mesh) return;
   if (mesh->d_elem) (void)hipFree(mesh->d_elem);
+  for (auto& o : mesh->order)
+    if (o.d_elem) (void)hipFree(o.d_elem);
   delete mesh;
 }
 
@@ -1265,7 +1350,7 @@ int dgd_workspace_size(const dgd_op* op, int32_t n_points, size_t* bytes) {
     if (!op || !bytes) fail(DGD_EINVAL, "NULL argument");
     if (n_points < 1) fail(DGD_EINVAL, "n_points must be >= 1");
     size_t off[9];
-    ws_layout(plain_target(op), n_points, bytes, off);
+    ws_layout(run_target(op, n_points), n_points, bytes, off);
     return DGD_OK;
   });
 }
@@ -1333,7 +1418,7 @@ int dgd_run_create(dgd_op* op, const double* points, int32_t n_points, double si
     if (!(sigma0_um >= 0) || !std::isfinite(sigma0_um)) fail(DGD_EINVAL, "sigma0 must be >= 0");
     check_points(op->mesh->host, points, n_points);
     check_axon_cells(op, points, n_points);
-    *out = run_create(plain_target(op), points, n_points, sigma0_um, d_ws, ws_bytes, hip_stream);
+    *out = run_create(run_target(op, n_points), points, n_points, sigma0_um, d_ws, ws_bytes, hip_stream);
     return DGD_OK;
   });
 }
@@ -1368,10 +1453,17 @@ int dgd_run_signal(dgd_run* run, const double* q, int32_t n_q, double* signal_ou
   });
 }
 
+// Mesh elements whose state a plain run's host buffers hold: the run's own
+// table may be class-sorted and padded (run_target), the host layout is
+// the mesh order.
+static int64_t mesh_elements(const dgd_run* run) {
+  return run->t.member_index ? (int64_t)(*run->t.member_index)[0].size() : run->t.E;
+}
+
 int dgd_run_shape(const dgd_run* run, int64_t* n_values, int32_t* n_points, int32_t* value_bytes) {
   return guarded([&]() -> int {
     if (!run) fail(DGD_EINVAL, "run is NULL");
-    if (n_values) *n_values = run->t.E * run->t.np * (int64_t)run->R;
+    if (n_values) *n_values = mesh_elements(run) * run->t.np * (int64_t)run->R;
     if (n_points) *n_points = run->R;
     if (value_bytes) *value_bytes = (int32_t)state_bytes(run->t.prec);
     return DGD_OK;
@@ -1381,12 +1473,23 @@ int dgd_run_shape(const dgd_run* run, int64_t* n_values, int32_t* n_points, int3
 int dgd_run_get_state(dgd_run* run, void* host_out, size_t bytes) {
   return guarded([&]() -> int {
     if (!run || !host_out) fail(DGD_EINVAL, "NULL argument");
-    const size_t n = (size_t)run->t.E * run->t.np * run->R * state_bytes(run->t.prec);
+    const RunTarget& t = run->t;
+    const size_t eb = (size_t)t.np * run->R * state_bytes(t.prec);   // bytes per element
+    const size_t n = (size_t)mesh_elements(run) * eb;
     if (bytes < n)
       fail(DGD_EINVAL, "state buffer of " + std::to_string(bytes) + " bytes; the run needs " +
                            std::to_string(n));
-    DGD_HIP_CHECK(hipMemcpyAsync(host_out, run->U, n, hipMemcpyDeviceToHost, run->stream));
+    if (!t.member_index) {
+      DGD_HIP_CHECK(hipMemcpyAsync(host_out, run->U, n, hipMemcpyDeviceToHost, run->stream));
+      DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+      return DGD_OK;
+    }
+    std::vector<char> buf((size_t)t.E * eb);
+    DGD_HIP_CHECK(hipMemcpyAsync(buf.data(), run->U, buf.size(), hipMemcpyDeviceToHost, run->stream));
     DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+    const std::vector<int64_t>& at = (*t.member_index)[0];
+    for (size_t e = 0; e < at.size(); ++e)
+      std::memcpy((char*)host_out + e * eb, &buf[(size_t)at[e] * eb], eb);
     return DGD_OK;
   });
 }
@@ -1395,10 +1498,21 @@ int dgd_run_set_state(dgd_run* run, const void* host_in, size_t bytes) {
   return guarded([&]() -> int {
     if (!run || !host_in) fail(DGD_EINVAL, "NULL argument");
     const RunTarget& t = run->t;
-    const size_t n = (size_t)t.E * t.np * run->R * state_bytes(t.prec);
+    const size_t eb = (size_t)t.np * run->R * state_bytes(t.prec);
+    const size_t n = (size_t)mesh_elements(run) * eb;
     if (bytes != n)
       fail(DGD_EINVAL, "state buffer of " + std::to_string(bytes) + " bytes; the run holds " +
                            std::to_string(n));
+    if (t.member_index) {
+      // padding elements of the sorted table stay zero
+      std::vector<char> buf((size_t)t.E * eb, 0);
+      const std::vector<int64_t>& at = (*t.member_index)[0];
+      for (size_t e = 0; e < at.size(); ++e)
+        std::memcpy(&buf[(size_t)at[e] * eb], (const char*)host_in + e * eb, eb);
+      DGD_HIP_CHECK(hipMemcpyAsync(run->U, buf.data(), buf.size(), hipMemcpyHostToDevice, run->stream));
+      DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+      return DGD_OK;
+    }
     if (t.form == 1) {
       // mixed form: u is zero in axon cells (k = 0, no flux in); the stage
       // kernels never touch those blocks, so they are cleared here
@@ -1490,7 +1604,7 @@ int dgd_eap_solve_noalloc(dgd_op* op, const double* points, int32_t n_points, do
     if (dev != op->mesh->device)
       fail(DGD_EINVAL, "the current device is not the one the operator was built on");
     const auto sched = schedule(deltas_ms, n_deltas, op->dt_nom);
-    const RunTarget t = plain_target(op);
+    const RunTarget t = run_target(op, n_points);
     size_t total, off[9];
     ws_layout(t, n_points, &total, off);
     if (total > kScratchBytes)
@@ -1672,12 +1786,17 @@ int dgd_batch_create(dgd_op* const* ops, int32_t n_geoms, const double* points, 
         std::vector<int> blk_geom, blk_start;
         grp.dt = 1e300;
         t.hosts.clear();
+        const int Gp = batch_pack(t, b->R);
+        std::vector<int4> tab;
+        grp.member_index.assign(grp.geoms.size(), {});
         for (int k = 0; k < (int)grp.geoms.size(); ++k) {
           const dgd_op* op = b->ops[grp.geoms[k]];
           const int64_t off = (int64_t)elem.size();
           t.hosts.emplace_back(&op->mesh->host, off);
           blk_start.push_back((int)(off / kReducePer));
-          for (const int4& e : op->mesh->packed) {
+          member_table(op->mesh, Gp, &tab, &grp.member_index[k]);
+          for (int64_t& i : grp.member_index[k]) i += off;
+          for (const int4& e : tab) {
             int4 c = e;
             if (c.x >= 0) c.x += (int)off;
             if (c.y >= 0) c.y += (int)off;
@@ -1695,6 +1814,7 @@ int dgd_batch_create(dgd_op* const* ops, int32_t n_geoms, const double* points, 
         blk_start.push_back((int)(elem.size() / kReducePer));
         if ((int64_t)elem.size() != t.E) fail(DGD_EINVAL, "internal: batch size mismatch");
         grp.E = t.E;
+        t.member_index = &grp.member_index;
         grp.d_elem = (int4*)upload(elem);
         grp.d_blk_geom = (int*)upload(blk_geom);
         grp.d_blk_start = (int*)upload(blk_start);

@@ -93,6 +93,15 @@ struct dgd_mesh {
   int device = 0;
   std::vector<int4> packed;  // [E] packed metadata (host copy)
   int4* d_elem = nullptr;    // [E] packed metadata on the device (uploaded on first use)
+  // Element tables of the packed stage kernel (order[0]: 2 elements per
+  // wave, order[1]: 4): elements grouped by class in windows and padded per
+  // class run (see member_table in abi.cpp), built with d_elem.
+  struct Order {
+    std::vector<int4> table;                     // host copy
+    std::vector<std::vector<int64_t>> index;     // [1][E]: table position of mesh element e
+    int4* d_elem = nullptr;
+  };
+  Order order[2];
 };
 
 struct dgd_op {
@@ -168,6 +177,9 @@ struct RunTarget {
   void* qbuf = nullptr;          // scratch q of the run, [E][2][np][R]
   // host mesh of each geometry and the row of its first element in the table
   std::vector<std::pair<const MeshHost*, int64_t>> hosts;
+  // batched runs: table position of each member's mesh elements, [member][e]
+  // (NULL: member g's element e sits at hosts[g].second + e)
+  const std::vector<std::vector<int64_t>>* member_index = nullptr;
 };
 
 }  // namespace dgd
@@ -212,6 +224,7 @@ struct dgd_batch {
     int64_t E = 0;                 // padded elements
     int64_t dof = 0;               // active DoF per right-hand side
     double dt = 0;                 // min of the members' nominal steps
+    std::vector<std::vector<int64_t>> member_index;   // [member][mesh element] -> table position
     dgd_run* run = nullptr;
   };
   std::vector<Group> groups;

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "launch.h"
 
@@ -700,8 +701,10 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
 // not, by zeroing the other product's vector: a product with an exact zero
 // vector leaves the accumulator unchanged (it never holds -0), so a lane
 // computes the same bits whatever the masks of the other elements of its
-// wave, and with all faces present (the common case) the F products are
-// skipped outright.  Waves whose elements mix the
+// wave.  A face's N product runs only if some lane's element has the face
+// and its F product only if some lane's element lacks it: runs stepped on
+// class-sorted element tables (one face mask per wave) do one of the two
+// per face, like a single element.  Waves whose elements mix the
 // two orientations (rare: meshes are ordered in orientation groups of four)
 // run once per orientation under a lane mask.  Modes and combine as in
 // k_stage (0 apply, 1 SSP-RK3 stage).  ABS: the operator has absorbing box
@@ -741,7 +744,19 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
       // whether any element misses a face
       const int o0 = __builtin_amdgcn_readfirstlane(o);
       const bool mixed = __ballot(o != o0) != 0;
+      // per face: whether some lane's element has it, and whether some
+      // lane's lacks it (from P2 up; with class-sorted element tables a wave
+      // holds one face mask, so only one of the two products below runs per
+      // face).  At P1 the products are cheap and the plain test is faster:
+      // N products always, F products when any element misses a face.
+      constexpr bool PER_FACE = NP > 3;
       const bool partial = __ballot(mask != 7) != 0;
+      bool has_any[3], lacks_any[3];
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        has_any[f] = PER_FACE ? __ballot((mask >> f) & 1) != 0 : true;
+        lacks_any[f] = PER_FACE ? __ballot(!((mask >> f) & 1)) != 0 : partial;
+      }
       const bool box0 = ABS && m.x == -2, box1 = ABS && m.y == -2;
       const bool any_box = ABS && __ballot(box0 || box1) != 0;
       // one element and right-hand side per lane with orientation oo (uniform)
@@ -779,16 +794,19 @@ __global__ void __launch_bounds__(256) k_stage_packed(const TS* __restrict__ us,
         }
 #define DGD_PFACE(F, SV)                                                                     \
         {                                                                                    \
-          const double* Nf = Nm + (oo * 3 + F) * NP * NP;                                    \
           const bool has = !partial || ((mask >> F) & 1);                                    \
-          double dn[NP];                                                                     \
-          _Pragma("unroll") for (int j = 0; j < NP; ++j) dn[j] = has ? (double)SV[j] - c : 0.0; \
-          _Pragma("unroll") for (int i = 0; i < NP; ++i) {                                   \
-            double a = acc[i];                                                               \
-            _Pragma("unroll") for (int j = 0; j < NP; ++j) a = fma(Nf[i * NP + j], dn[j], a); \
-            acc[i] = a;                                                                      \
+          if (has_any[F]) {                                                                  \
+            const double* Nf = Nm + (oo * 3 + F) * NP * NP;                                  \
+            double dn[NP];                                                                   \
+            _Pragma("unroll") for (int j = 0; j < NP; ++j)                                   \
+              dn[j] = has ? (double)SV[j] - c : 0.0;                                         \
+            _Pragma("unroll") for (int i = 0; i < NP; ++i) {                                 \
+              double a = acc[i];                                                             \
+              _Pragma("unroll") for (int j = 0; j < NP; ++j) a = fma(Nf[i * NP + j], dn[j], a); \
+              acc[i] = a;                                                                    \
+            }                                                                                \
           }                                                                                  \
-          if (partial) {                                                                     \
+          if (lacks_any[F]) {                                                                \
             const double* Ff = Fm + (oo * 3 + F) * NP * NP;                                  \
             double dm[NP];                                                                   \
             _Pragma("unroll") for (int j = 0; j < NP; ++j) dm[j] = has ? 0.0 : d[j];         \

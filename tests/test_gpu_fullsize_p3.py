@@ -79,3 +79,27 @@ def test_fullsize_p3_rk3_matrix_cores_first_delta(case):
     assert err.max() < 1e-4
     assert drift < 1e-5
     op.close()
+
+
+def test_fullsize_p3_rk3_valu_first_delta(case):
+    """The kernel the P3 benchmark runs when the autotuner prefers the FP64
+    vector path: k_stage<float, 10> at 128 right-hand sides (two 64-column
+    chunks per element), RK3 over the first Delta."""
+    dgd, c, gold, mesh, pts, idx = case
+    say(f"full-size P3 RK3 on the vector kernel: dt {gold['dt_nom']:.4e} ms to Delta "
+        f"{gold['deltas'][0]} ms, {pts.shape[0]} right-hand sides")
+    op = dgd.Operator(mesh, 3, c["D"], c["eta"], dgd.DGD_FP32, dt_max_ms=gold["dt_nom"])
+    dgd.dgd_set_option("p3_mfma", 0)
+    try:
+        run = dgd.Run(op, pts, c["sigma0"])
+        assert dgd.dgd_run_kernel(run.handle)[0] == "valu"
+        run.close()
+        sig, mom = op.solve(pts, c["sigma0"], gold["deltas"][:1])
+    finally:
+        dgd.dgd_set_option("p3_mfma", 2)
+    err = omom.rel_err(sig[idx], omom.sigma_a(np.asarray(gold["moments"])[:, :1]))
+    drift = np.abs(mom[..., 0] - 1).max()
+    say(f"  max rel err vs oracle {err.max():.2e}; |M0-1| {drift:.2e}")
+    assert err.max() < 1e-4
+    assert drift < 1e-5
+    op.close()

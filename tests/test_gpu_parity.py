@@ -140,6 +140,64 @@ def test_fp32_parity_dense_packing(dgd, p):
     assert err.max() < 1e-4
 
 
+def _near_wall_points(g, n_random, seed):
+    """Start points in active cells that touch a removed cell (or the box
+    edge), 0.4 h from the cell centre toward the wall, and the retained mass
+    of each point's pulse (share of a 20k-sample Gaussian, sigma0 = 0.3 um,
+    landing on active cells): n_random of them at random plus the one that
+    keeps the least mass."""
+    m = omesh.build_mesh(g.L, g.N, g.disks)
+    act, N, h = m.active_cell, g.N, g.h if hasattr(g, "h") else g.L / g.N
+    cand = []
+    for i in range(N):
+        for j in range(N):
+            if not act[i, j]:
+                continue
+            for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                ni, nj = i + di, j + dj
+                if 0 <= ni < N and 0 <= nj < N and not act[ni, nj]:
+                    cand.append(((i + 0.5 + 0.4 * di) * h, (j + 0.5 + 0.4 * dj) * h))
+    cand = np.asarray(cand)
+    z = np.random.default_rng(seed).normal(size=(20000, 2)) * 0.3
+
+    def kept(x):
+        q = x[None, :] + z
+        inside = (q[:, 0] >= 0) & (q[:, 0] < g.L) & (q[:, 1] >= 0) & (q[:, 1] < g.L)
+        ci = np.clip((q[:, 0] / h).astype(int), 0, N - 1)
+        cj = np.clip((q[:, 1] / h).astype(int), 0, N - 1)
+        return float((inside & act[ci, cj]).mean())
+
+    frac = np.array([kept(x) for x in cand])
+    rng = np.random.default_rng(seed + 1)
+    pick = list(rng.choice(cand.shape[0], n_random, replace=False)) + [int(np.argmin(frac))]
+    return cand[pick], frac[pick]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_near_wall_pulses(dgd, prec):
+    """Pulses started next to the staircase walls, one of them in a gap where
+    most of its Gaussian falls on removed cells and is discarded before the
+    unit-mass normalisation (initial-data reading R8): Sigma against the
+    oracle's RK3 at the same step, 1e-10 (FP64) and 1e-4 (FP32)."""
+    g = make_geometry(10.0, 40, 19070619 + 77, phi=0.65)
+    pts, frac = _near_wall_points(g, 5, 19070619 + 78)
+    say(f"near-wall pulses {prec}: retained mass {np.round(frac, 3).tolist()}")
+    assert frac.min() < 0.5
+    deltas = [0.02, 0.05]
+    prob = osolve.prepare(g.L, g.N, g.disks, 2, 2.0, 10.0)
+    dt = prob.dt["dt_nom"]
+    ref = osolve.solve(prob, pts, 0.3, deltas, method="rk3")
+    mesh = dgd.Mesh(g.L, g.N, g.disks)
+    pr = dgd.DGD_FP64 if prec == "fp64" else dgd.DGD_FP32
+    op = dgd.Operator(mesh, 2, 2.0, 10.0, pr, dt_max_ms=dt)
+    sig, mom = op.solve(pts, 0.3, deltas)
+    err = omom.rel_err(sig, omom.sigma_a(ref))
+    say(f"  max rel err {err.max():.2e}; |M0-1| {np.abs(mom[..., 0] - 1).max():.2e}")
+    assert err.max() < (1e-10 if prec == "fp64" else 1e-4)
+    op.close()
+    mesh.close()
+
+
 def test_determinism_graphs_and_checkpoint(dgd):
     """Two runs are bitwise equal (no atomics); graph replay equals plain
     launches bitwise; a state saved and restored into a new run continues
