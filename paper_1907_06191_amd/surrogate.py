@@ -1,7 +1,8 @@
 """Surrogate driver: DG-generated training data, ensemble training, and
 prediction with DG fallback -- all arithmetic in libdgd's kernels.
 
-    python -m paper_1907_06191_amd.surrogate --train-geoms 512 --test-geoms 128
+    python -m paper_1907_06191_amd.surrogate --train-geoms 1250 --test-geoms 128 \
+        --epochs 20 --weights surrogate_weights.npz --out report.json
 
 Data recipe.  Geometries follow the batched workload's recipe (packing
 fraction ~ U(0.4, 0.7), Gamma shape ~ U(3, 6), mean ~ U(0.4, 0.7) um,
@@ -66,8 +67,12 @@ def geometries(ids, workers=8, grid=GRID):
 
 
 def dg_targets(geos, deltas, p=1, dt_max=0.0, chunk=64, label="DG"):
-    """Batched DG solves of the geometries, `chunk` per batch; returns
-    (images [G][64][64], targets [G][nDelta][3], seconds of the solves)."""
+    """Batched DG solves of the geometries, `chunk` per batch.  Returns
+    (images [G][64][64], targets [G][nDelta][3], halves [2][G][nDelta][3],
+    seconds of the solves): the target is the mean over the 16 start points
+    of Sigma / (2 D Delta) as (xx, xy, yy); `halves` are the same means over
+    start points 0..7 and 8..15 (their half-difference measures the
+    sampling noise of the 16-point target)."""
     meshes = [dgd.Mesh(g.L, g.N, g.disks) for g, _ in geos]
     ops = [dgd.Operator(m, p, D, ETA, dgd.DGD_FP32, dt_max_ms=dt_max) for m in meshes]
     pts = np.stack([pp for _, pp in geos])
@@ -80,11 +85,31 @@ def dg_targets(geos, deltas, p=1, dt_max=0.0, chunk=64, label="DG"):
         sig.append(s)
         print(f"{label}: {min(i + chunk, len(ops))}/{len(ops)} geometries solved, {el:.0f}s",
               flush=True)
-    sig = np.concatenate(sig)
+    sig = np.concatenate(sig)                                  # [G][16][nDelta][3]
     scale = 2.0 * D * np.asarray(deltas)[None, :, None]
-    targets = sig.mean(axis=1) / scale                       # [G][nDelta][3]
+    targets = sig.mean(axis=1) / scale
+    halves = np.stack([sig[:, :8].mean(axis=1) / scale, sig[:, 8:].mean(axis=1) / scale])
     images = np.stack([dgd.dgd_mesh_occupancy(m.handle, GRID) for m in meshes])
-    return images, targets, el
+    for o in ops:
+        o.close()
+    for m in meshes:
+        m.close()
+    return images, targets, halves, el
+
+
+def augment(images, targets):
+    """The mesh's exact symmetries: the transpose (x, y) -> (y, x) maps the
+    pixel triangulation to itself (its diagonals run along x = y) and swaps
+    Sigma_xx and Sigma_yy; the half turn (x, y) -> (L - x, L - y) maps it to
+    itself (T0 <-> T1) and leaves Sigma unchanged.  Transposed or rotated
+    start points give exactly these Sigma, so the four images of a geometry
+    under {identity, transpose, half turn, both} are exact DG samples."""
+    t_sw = targets[..., ::-1]
+    tr = np.swapaxes(images, 1, 2)
+    rot = images[:, ::-1, ::-1]
+    both = np.swapaxes(rot, 1, 2)
+    return (np.concatenate([images, tr, rot, both]),
+            np.concatenate([targets, t_sw, targets, t_sw]))
 
 
 def flatten(images, targets, deltas):
@@ -94,60 +119,127 @@ def flatten(images, targets, deltas):
     return im, ld, targets.reshape(G * nd, 3)
 
 
+def rel_err(a, b):
+    """Frobenius norm of the symmetric 2 x 2 difference over that of b, per
+    row of (xx, xy, yy)."""
+    num = np.sqrt(((a - b) ** 2).sum(-1) + (a[..., 1] - b[..., 1]) ** 2)
+    den = np.sqrt((b ** 2).sum(-1) + b[..., 1] ** 2)
+    return num / den
+
+
+def evaluate(s, images, targets, halves, deltas, dg_seconds, thresholds):
+    """Surrogate against the DG judge on held-out geometries: error of the
+    ensemble mean, the 16-point target's sampling noise (half the distance
+    between the two 8-point halves), and per spread threshold the fallback
+    rate, the error of the accepted answers and the gain in queries per
+    second over answering every query with the DG solve."""
+    import torch
+    X, Lq, Y = flatten(images, targets, deltas)
+    n = Y.shape[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mean, spread, _ = s.predict(X, Lq, threshold=thresholds[0])
+    t_pred = time.perf_counter() - t0
+    err = rel_err(mean, Y)
+    noise = rel_err(0.5 * (halves[0] - halves[1]).reshape(n, 3) + Y, Y)
+    G, nd = targets.shape[:2]
+    # a fallback needs its geometry's DG solve up to that Delta: the time of
+    # a solve grows linearly with the last Delta it reaches (fixed step)
+    t_geo = dg_seconds / G
+    dl = np.asarray(deltas)
+    rep = {"n_queries": n, "predict_seconds": t_pred, "dg_seconds": dg_seconds,
+           "dg_queries_per_s": n / dg_seconds, "surrogate_only_queries_per_s": n / t_pred,
+           "rel_err_median": float(np.median(err)), "rel_err_p95": float(np.percentile(err, 95)),
+           "noise_floor_median": float(np.median(noise)),
+           "noise_floor_p95": float(np.percentile(noise, 95)),
+           "spread_median": float(np.median(spread)), "by_threshold": []}
+    for thr in thresholds:
+        fb = spread > thr
+        frac = float(fb.mean())
+        need = np.where(fb.reshape(G, nd), dl[None, :], 0.0).max(axis=1) / dl[-1]
+        t_total = t_pred + t_geo * float(need.sum())
+        acc = ~fb
+        rep["by_threshold"].append({
+            "threshold": thr, "fallback_rate": frac, "gain": dg_seconds / t_total,
+            "geometries_solved": int((need > 0).sum()),
+            "accepted": int(acc.sum()),
+            "accepted_rel_err_median": float(np.median(err[acc])) if acc.any() else None,
+            "accepted_rel_err_max": float(err[acc].max()) if acc.any() else None,
+            "answer_rel_err_median": float(np.median(np.where(fb, 0.0, err)))})
+    return rep, mean, spread
+
+
+THRESHOLDS = [1e-3, 3e-3, 1e-2, 3e-2, 1e-1]
+TEST_FIRST = 1250       # held-out geometries are numbered from here
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train-geoms", type=int, default=512)
+    ap.add_argument("--train-geoms", type=int, default=1250)
     ap.add_argument("--test-geoms", type=int, default=128)
     ap.add_argument("--members", type=int, default=4)
-    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--threshold", type=float, default=1e-3)
+    ap.add_argument("--no-augment", dest="augment", action="store_false")
     ap.add_argument("--workers", type=int, default=16)
-    ap.add_argument("--out", default=None)
+    ap.add_argument("--save-data", default=None, help="write the DG data set here (.npz) and stop")
+    ap.add_argument("--load-data", default=None, help="read the DG data set from here (.npz)")
+    ap.add_argument("--weights", default=None, help="write the trained members here (.npz)")
+    ap.add_argument("--out", default=None, help="write the report here (.json)")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     deltas = deltas_default()
-    rep = {"grid": GRID, "p": 1, "deltas_ms": list(deltas)}
-    t0 = time.time()
-    train = geometries(range(args.train_geoms), args.workers)
-    test = geometries(range(args.train_geoms, args.train_geoms + args.test_geoms), args.workers)
-    rep["geometry_seconds"] = time.time() - t0
-    print(f"geometries: {len(train)} train, {len(test)} test in {rep['geometry_seconds']:.0f}s", flush=True)
-    im_tr, tg_tr, t_tr = dg_targets(train, deltas, label="DG train")
-    im_te, tg_te, t_te = dg_targets(test, deltas, label="DG test")
+    rep = {"grid": GRID, "p": 1, "deltas_ms": list(deltas), "augment": args.augment,
+           "train_geoms": args.train_geoms, "test_geoms": args.test_geoms, "epochs": args.epochs}
+    if args.load_data:
+        z = np.load(args.load_data)
+        im_tr, tg_tr, hv_tr, im_te, tg_te, hv_te = (z[k] for k in
+                                                     ("im_tr", "tg_tr", "hv_tr", "im_te", "tg_te", "hv_te"))
+        t_tr, t_te = float(z["t_tr"]), float(z["t_te"])
+        rep["train_geoms"], rep["test_geoms"] = int(im_tr.shape[0]), int(im_te.shape[0])
+    else:
+        t0 = time.time()
+        train = geometries(range(args.train_geoms), args.workers)
+        test = geometries(range(TEST_FIRST, TEST_FIRST + args.test_geoms), args.workers)
+        rep["geometry_seconds"] = time.time() - t0
+        print(f"geometries: {len(train)} train, {len(test)} test in {rep['geometry_seconds']:.0f}s",
+              flush=True)
+        im_tr, tg_tr, hv_tr, t_tr = dg_targets(train, deltas, label="DG train")
+        im_te, tg_te, hv_te, t_te = dg_targets(test, deltas, label="DG test")
+        if args.save_data:
+            np.savez_compressed(args.save_data, im_tr=im_tr, tg_tr=tg_tr, hv_tr=hv_tr, im_te=im_te,
+                                tg_te=tg_te, hv_te=hv_te, t_tr=t_tr, t_te=t_te)
+            print(f"wrote {args.save_data}", flush=True)
+            return
     rep["dg_seconds_train"] = t_tr
     rep["dg_seconds_test"] = t_te
-    print(f"DG data: train {t_tr:.0f}s, test {t_te:.0f}s", flush=True)
+    noise_tr = rel_err(0.5 * (hv_tr[0] - hv_tr[1]) + tg_tr, tg_tr)
+    rep["train_noise_floor_median"] = float(np.median(noise_tr))
+    if args.augment:
+        im_tr, tg_tr = augment(im_tr, tg_tr)
     X, L, Y = flatten(im_tr, tg_tr, deltas)
+    rep["train_samples"] = int(Y.shape[0])
     s = dgd.Surrogate(n_members=args.members, channels=32, hidden=256, seed=1907)
     t0 = time.perf_counter()
-    losses = s.train(X, L, Y, epochs=args.epochs, batch=args.batch, lr=args.lr, shuffle_seed=619)
+    # one epoch per call (the optimizer state persists in the surrogate), a
+    # cosine-decayed step size, a fresh shuffle each epoch
+    for e in range(args.epochs):
+        lr = args.lr * max(0.5 * (1.0 + np.cos(np.pi * e / args.epochs)), 0.05)
+        losses = s.train(X, L, Y, epochs=1, batch=args.batch, lr=lr, shuffle_seed=619 + 7919 * e)
+        print(f"epoch {e + 1}/{args.epochs}: lr {lr:.2e}, train loss {losses[:, -1]}, "
+              f"{time.perf_counter() - t0:.0f}s", flush=True)
     rep["train_seconds"] = time.perf_counter() - t0
-    rep["final_train_loss"] = losses[:, -1].tolist()
-    print(f"trained {args.members} members in {rep['train_seconds']:.0f}s, loss {losses[:, -1]}", flush=True)
-    Xt, Lt, Yt = flatten(im_te, tg_te, deltas)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    mean, spread, fb = s.predict(Xt, Lt, threshold=args.threshold)
-    t_pred = time.perf_counter() - t0
-    err = np.sqrt(((mean - Yt) ** 2).sum(1) + (mean[:, 1] - Yt[:, 1]) ** 2) / \
-        np.sqrt((Yt ** 2).sum(1) + Yt[:, 1] ** 2)
-    n = Yt.shape[0]
-    frac_fb = float(fb.mean())
-    # time per query: DG-only = the test set's batched DG time per (geometry, Delta)
-    dg_per_query = t_te / n
-    sur_per_query = t_pred / n + frac_fb * dg_per_query
-    rep.update(
-        n_test_queries=n, predict_seconds=t_pred, fallback_rate=frac_fb,
-        rel_err_all_median=float(np.median(err)), rel_err_all_p95=float(np.percentile(err, 95)),
-        rel_err_accepted_max=float(err[~fb].max()) if (~fb).any() else None,
-        rel_err_accepted_median=float(np.median(err[~fb])) if (~fb).any() else None,
-        spread_median=float(np.median(spread)),
-        dg_queries_per_s=1.0 / dg_per_query, surrogate_queries_per_s=1.0 / sur_per_query,
-        gain=dg_per_query / sur_per_query)
+    rep["train_loss"] = losses[:, -1].tolist()
+    print(f"trained {args.members} members on {Y.shape[0]} samples in {rep['train_seconds']:.0f}s, "
+          f"loss {losses[:, -1]}", flush=True)
+    ev, _, _ = evaluate(s, im_te, tg_te, hv_te, deltas, t_te, THRESHOLDS)
+    rep["test"] = ev
     print(json.dumps(rep), flush=True)
+    if args.weights:
+        np.savez(args.weights, **{f"member{k}": dgd.dgd_surrogate_get_params(s.handle, k)
+                                  for k in range(args.members)})
     if args.out:
         with open(args.out, "w") as f:
             json.dump(rep, f, indent=1)
