@@ -217,27 +217,72 @@ __global__ void k_split_feat(const float* __restrict__ dfeat, float* __restrict_
   dp4[t] = dfeat[(int64_t)b * (F + 1) + k];
 }
 
-// C[m][n] = sum_k A(m, k) B(k, n), A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn];
-// 16 x 16 output tile per workgroup, k in LDS chunks of 16, fixed order.
+// C[m][n] = sum_k A(m, k) B(k, n), A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn]
+// (every dense layer's forward and backward product), on the matrix cores:
+// a workgroup of four waves computes a 64 x 64 tile of C, each wave a
+// 32 x 32 quarter as 2 x 2 blocks of v_mfma_f32_16x16x4_f32; K runs in
+// chunks of 16 staged through LDS (zero-filled past M, N, K), four MFMA
+// k-steps per chunk, in a fixed order.  Operand layout of one MFMA: lane l
+// holds A[m = l % 16][k = l / 16] and B[k = l / 16][n = l % 16] and
+// receives D[m = 4 (l / 16) + i][n = l % 16], i < 4.
+constexpr int GT = 64;    // C tile edge per workgroup
+constexpr int GK = 16;    // K chunk
 __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, const float* __restrict__ Bm,
                                               float* __restrict__ C, int M, int N, int K,
                                               int64_t sam, int64_t sak, int64_t sbk, int64_t sbn,
                                               int ldc) {
-  __shared__ float As[16][17], Bs[16][17];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  const int m = blockIdx.y * 16 + ty, n = blockIdx.x * 16 + tx;
-  float acc = 0.f;
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const int am = blockIdx.y * 16 + ty, ak = k0 + tx;
-    As[ty][tx] = (am < M && ak < K) ? A[am * sam + ak * sak] : 0.f;
-    const int bk = k0 + ty, bn = blockIdx.x * 16 + tx;
-    Bs[ty][tx] = (bk < K && bn < N) ? Bm[bk * sbk + bn * sbn] : 0.f;
+  typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+  __shared__ float As[GT][GK + 1];
+  __shared__ float Bs[GK][GT + 1];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;      // wave's quarter of the tile
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  const int lr = lane & 15, lk = lane >> 4;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    // stage A[m0 .. m0+63][k0 .. k0+15] and B[k0 .. k0+15][n0 .. n0+63]:
+    // 1024 values each, four per thread
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = t + 256 * q;
+      const int am = idx / GK, ak = idx % GK;
+      const int gm = m0 + am, gk = k0 + ak;
+      As[am][ak] = (gm < M && gk < K) ? A[gm * sam + gk * sak] : 0.f;
+      const int bk = idx / GT, bn = idx % GT;
+      const int hk = k0 + bk, hn = n0 + bn;
+      Bs[bk][bn] = (hk < K && hn < N) ? Bm[hk * sbk + hn * sbn] : 0.f;
+    }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc += As[ty][k] * Bs[k][tx];
+    for (int st = 0; st < GK / 4; ++st) {
+      const int kk = 4 * st + lk;
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[wm + 16 * i + lr][kk];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[kk][wn + 16 * j + lr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
     __syncthreads();
   }
-  if (m < M && n < N) C[(int64_t)m * ldc + n] = acc;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + 4 * lk + r, n = n0 + wn + 16 * j + lr;
+        if (m < M && n < N) C[(int64_t)m * ldc + n] = acc[i][j][r];
+      }
 }
 
 // z[b][n] += bias[n]; a = relu(z) (relu off: a = z)
@@ -399,7 +444,8 @@ struct Acts {
 
 void gemm(const float* A, const float* B, float* C, int M, int N, int K, int64_t sam, int64_t sak,
           int64_t sbk, int64_t sbn, int ldc, hipStream_t st) {
-  k_gemm<<<dim3((N + 15) / 16, (M + 15) / 16), 256, 0, st>>>(A, B, C, M, N, K, sam, sak, sbk, sbn, ldc);
+  k_gemm<<<dim3((N + GT - 1) / GT, (M + GT - 1) / GT), 256, 0, st>>>(A, B, C, M, N, K, sam, sak, sbk,
+                                                                     sbn, ldc);
 }
 
 void conv_fwd(const float* x, const float* w, const float* b, float* z, float* a, int B, int Ci,
