@@ -47,8 +47,9 @@ HBM_PEAK_GBS = 8000.0
 # per wave, waves, XCD order, workgroups): a changed kernel source or
 # another tuned shape reports traffic null.  Summaries: profiles/.
 MEASURED_TRAFFIC = {
-    ("pack512-p2", "k_stage<float,6>", "280047a4b8896864", (2, 4, 0, 26674)): 1147.8e6,
-    ("pack256-p3", "k_stage<float,10>", "280047a4b8896864", (4, 2, 1, 5984)): 819.5e6,
+    ("pack512-p2", "k_stage<float,6>", "16abf2790a26ceac", (2, 4, 0, 26674)): 1129.6e6,
+    ("pack512-p2", "k_stage<float,3>", "16abf2790a26ceac", (2, 4, 0, 26674)): 566.5e6,
+    ("pack256-p3", "k_stage<float,10>", "16abf2790a26ceac", (2, 1, 1, 23936)): 660.3e6,
 }
 
 

@@ -169,6 +169,35 @@ def evaluate(s, images, targets, halves, deltas, dg_seconds, thresholds):
     return rep, mean, spread
 
 
+def speed(members=4, n=8192):
+    """Throughput of the training and inference kernels on synthetic data:
+    one epoch over n random occupancy images (after a warm-up epoch on 512),
+    then prediction of 2n queries in batches of 4096."""
+    import torch
+    rng = np.random.default_rng(5)
+    imgs = (rng.random((n, GRID, GRID)) < 0.5).astype(np.uint8)
+    ld = rng.uniform(0, np.log(50), n)
+    tg = rng.uniform(0.2, 0.8, (n, 3))
+    s = dgd.Surrogate(n_members=members, channels=32, hidden=256, seed=1)
+    s.train(imgs[:512], ld[:512], tg[:512], epochs=1, batch=256)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.train(imgs, ld, tg, epochs=1, batch=256)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    print(f"train: {members * n / t:.0f} sample-passes/s ({t:.2f}s for {members} members x {n})",
+          flush=True)
+    big, bl = np.repeat(imgs, 2, axis=0), np.repeat(ld, 2)
+    s.predict(big[:4096], bl[:4096])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.predict(big, bl)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    print(f"predict: {big.shape[0] / t:.0f} queries/s ({members} members, batches of 4096)", flush=True)
+    s.close()
+
+
 THRESHOLDS = [1e-3, 3e-3, 1e-2, 3e-2, 1e-1]
 TEST_FIRST = 1250       # held-out geometries are numbered from here
 
@@ -187,9 +216,14 @@ def main():
     ap.add_argument("--load-data", default=None, help="read the DG data set from here (.npz)")
     ap.add_argument("--weights", default=None, help="write the trained members here (.npz)")
     ap.add_argument("--out", default=None, help="write the report here (.json)")
+    ap.add_argument("--speed", action="store_true",
+                    help="only time training and prediction on synthetic data and stop")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
+    if args.speed:
+        speed(args.members)
+        return
     deltas = deltas_default()
     rep = {"grid": GRID, "p": 1, "deltas_ms": list(deltas), "augment": args.augment,
            "train_geoms": args.train_geoms, "test_geoms": args.test_geoms, "epochs": args.epochs}

@@ -91,3 +91,27 @@ def test_fullsize_expm_all_deltas(case):
     say(f"  {napp} operator applications; max rel err vs oracle {err.max():.2e}")
     assert err.max() < 1e-8
     op.close()
+
+
+@pytest.mark.skipif(os.environ.get("DGD_LONG") != "1",
+                    reason="about 6 minutes of GPU time: run with DGD_LONG=1")
+def test_fullsize_rk3_fp32_all_deltas_r16(case):
+    """The whole 50 ms schedule of the 512^2 P2 workload by RK3 (about 2.26
+    million steps): the 8 stored start points and the 8 following ones as
+    16 right-hand sides (the packed stage kernel), every Delta against the
+    oracle's exact flow; 1e-4 on Sigma, mass within 1e-5."""
+    dgd, c, gold, mesh, pts, idx = case
+    sel = np.sort(np.concatenate([idx, idx + 1]))
+    pos = np.searchsorted(sel, idx)
+    say(f"full-size RK3 P2 FP32, 16 right-hand sides, {len(gold['deltas'])} Delta to "
+        f"{gold['deltas'][-1]:.0f} ms, dt {gold['dt_nom']:.4e} ms")
+    op = dgd.Operator(mesh, gold["p"], c["D"], c["eta"], dgd.DGD_FP32, dt_max_ms=gold["dt_nom"])
+    sig, mom = op.solve(pts[sel], c["sigma0"], gold["deltas"])
+    ref = omom.sigma_a(np.asarray(gold["moments"]))
+    err = omom.rel_err(sig[pos], ref)
+    drift = np.abs(mom[..., 0] - 1).max()
+    say(f"  max rel err vs oracle {err.max():.2e} (per Delta {np.round(err.max(axis=0), 8).tolist()}); "
+        f"|M0-1| {drift:.2e}")
+    assert err.max() < 1e-4
+    assert drift < 1e-5
+    op.close()
