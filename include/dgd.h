@@ -108,8 +108,10 @@ void dgd_mesh_destroy(dgd_mesh* mesh);
  * Build the SIPG operator of degree p on the mesh (section 3.1 with the
  * interior-penalty flux; section 3.2 for the role of the flux).
  *   p in {1, 2, 3}; D > 0 (um^2/ms); eta > 0 (penalty eta p^2 D / h);
- *   precision: DGD_FP64 or DGD_FP32 (state precision; with DGD_FP32, P3
- *     stages run on matrix cores when the right-hand-side count allows);
+ *   precision: DGD_FP64 or DGD_FP32 (state precision; with DGD_FP32 and a
+ *     right-hand-side count that is a multiple of 16, P3 stages may run on
+ *     matrix cores: option "p3_mfma", by default only where the autotuner
+ *     timed them faster than the FP64 vector kernel);
  *   dt_max_ms > 0: nominal step = min(0.1 h^2 / (D (p+1)^2), dt_max_ms);
  *   dt_max_ms <= 0: nominal step = min(0.1 h^2 / (D (p+1)^2), 0.9 X / b),
  *     X = 2.5127... the real stability limit of SSP-RK3 and
