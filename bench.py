@@ -325,6 +325,14 @@ def batched(args):
                           "steps_full_solve": nsteps})
     mom = b.moments(check=False)
     value = total_updates / (total_ms * 1e-3) / 1e9
+    # algorithmic bytes per launch: 32 B per DoF-update / 3 launches per step
+    for gr, pg in zip(groups, per_group):
+        launch_ms = pg["ms_per_step"] / 3
+        byts = 32.0 / 3.0 * gr["dof"] * R
+        pg["roofline"] = {"bound": "hbm", "achieved": round(byts / (launch_ms * 1e-3) / 1e9, 1),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(byts / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "bytes_per_launch": byts, "launch_ms": round(launch_ms, 5)}
     out = base_record(args, value, total_ms / args.steps, "f64 arithmetic, f32 state", {
         "workload": f"batch256-p12: batched solve, {n} geometries (grid edge 128..512 at h=100/512 um, "
                     f"phi 0.4..0.7), P1/P2 groups, {R} start points each",

@@ -444,7 +444,14 @@ void dgd_surrogate_destroy(dgd_surrogate* s);
  *   "autotune"     1 (default) = runs take the tuned stage launch shape of
  *                  their key, tuning it when the run is created if the key
  *                  is new; 0 = the shape options above
- * Errors: EINVAL for an unknown name or a value out of range. */
+ * Errors: EINVAL for an unknown name or a value out of range.
+ *
+ * Environment: DGD_RUN_LOG = a file to which every dgd_eap_solve,
+ * dgd_eap_solve_noalloc and dgd_eap_solve_batch appends one JSON line
+ * (configuration, step rule, steps, wall time, update rate, status, mass
+ * drift, the start-point mean of Sigma per Delta); DGD_TUNE_CACHE = a file
+ * holding the launch-shape table (the text of dgd_tune_export), read before
+ * the first lookup and rewritten after every newly tuned key. */
 int dgd_set_option(const char* name, int64_t value);
 
 /*

@@ -54,7 +54,9 @@ def build(verbose: bool = True, jobs: int = 8) -> str:
     while procs:
         _wait(procs.pop(0), verbose)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, "-shared", "-o", tmp, *objs]
+    # roctx: named ranges around the solve's phases for rocprofv3 traces
+    cmd = [hipcc(), *FLAGS, "-shared", "-o", tmp, *objs, "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
+           "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout)

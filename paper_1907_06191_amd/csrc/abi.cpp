@@ -18,6 +18,12 @@
 #include <unordered_map>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+
 #include "dgd_internal.h"
 #include "launch.h"
 #include "tune.h"
@@ -522,6 +528,72 @@ double power_lambda(dgd_op* op, int iters) {
   }
 }
 
+// Named range around a phase of a solve (roctx: visible in rocprofv3
+// traces with --marker-trace, free otherwise).
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+
+// One JSON line per solve appended to the file named by DGD_RUN_LOG (if
+// set): entry point, configuration (of the first geometry for a batch),
+// step rule, steps (of the longest group), wall time, update rate, status,
+// mass drift and the start-point mean of Sigma per Delta.  moments:
+// [n_points][n_deltas][6] (all geometries' start points for a batch), or
+// NULL; entries a failed solve did not reach (M0 = 0) are left out.
+void log_run(const char* entry, const dgd_op* op, int n_geoms, int64_t elements, int n_points,
+             const double* deltas, int n_deltas, int64_t steps, double updates, double seconds,
+             int status, const double* moments, const char* kernel) {
+  const char* path = std::getenv("DGD_RUN_LOG");
+  if (!path || !*path || !op) return;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  std::FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "{\"entry\": \"%s\", \"p\": %d, \"precision\": \"%s\", \"form\": \"%s\", "
+               "\"outer\": \"%s\", \"geometries\": %d, \"elements\": %lld, \"n_points\": %d, "
+               "\"deltas_ms\": [",
+               entry, op->ref.p, op->precision == DGD_FP64 ? "fp64" : "fp32",
+               op->form == 1 ? "mixed" : "primal", op->outer == DGD_OUTER_ABSORB ? "absorb" : "reflect",
+               n_geoms, (long long)elements, n_points);
+  for (int k = 0; k < n_deltas; ++k) std::fprintf(f, "%s%.17g", k ? ", " : "", deltas[k]);
+  std::fprintf(f, "], \"dt_ms\": %.17g, \"dt_rule\": \"%s\", \"lambda_max_per_ms\": %.17g, "
+               "\"steps\": %lld, \"seconds\": %.6f, \"gdof_updates_per_s\": %.6g, "
+               "\"kernel\": \"%s\", \"status\": %d",
+               op->dt_nom, op->dt_rule, op->lambda_max, (long long)steps, seconds,
+               seconds > 0 ? updates / seconds / 1e9 : 0.0, kernel ? kernel : "", status);
+  if (moments) {
+    double drift = 0;
+    std::fprintf(f, ", \"sigma_mean\": [");
+    for (int k = 0; k < n_deltas; ++k) {
+      double sx = 0, sy = 0, sz = 0;
+      int n = 0;
+      for (int r = 0; r < n_points; ++r) {
+        const double* m = moments + ((size_t)r * n_deltas + k) * 6;
+        if (!(m[0] != 0) || !std::isfinite(m[0])) continue;
+        drift = std::max(drift, std::fabs(m[0] - 1.0));
+        sx += m[3] / m[0];
+        sy += m[4] / m[0];
+        sz += m[5] / m[0];
+        ++n;
+      }
+      if (n)
+        std::fprintf(f, "%s[%.10g, %.10g, %.10g]", k ? ", " : "", sx / n, sy / n, sz / n);
+      else
+        std::fprintf(f, "%snull", k ? ", " : "");
+    }
+    std::fprintf(f, "], \"max_mass_drift\": %.6g", drift);
+  }
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
 // ---------------------------------------------------------------- runs ----
 
 void ws_layout(const RunTarget& t, int R, size_t* total, size_t off[9]) {
@@ -619,6 +691,7 @@ void init_point_mass(dgd_run* run) {
 // refused (their upload allocates).
 dgd_run* run_create(const RunTarget& t, const double* x0, int R, double sigma0, void* d_ws,
                     size_t ws_bytes, void* hip_stream, bool no_alloc = false) {
+  Range range("dgd:run_create");
   size_t total, off[9];
   ws_layout(t, R, &total, off);
   if (no_alloc && (!d_ws || sigma0 == 0))
@@ -743,6 +816,7 @@ hipGraphExec_t step_graph(dgd_run* run, int64_t n, double dt) {
 }
 
 void run_advance(dgd_run* run, int64_t n_steps, double dt) {
+  Range range("dgd:advance");
   if (n_steps < 0) fail(DGD_EINVAL, "n_steps must be >= 0");
   if (!(dt > 0) || !std::isfinite(dt)) fail(DGD_EINVAL, "dt must be positive");
   if (n_steps == 0) return;
@@ -764,6 +838,7 @@ void run_advance(dgd_run* run, int64_t n_steps, double dt) {
 // FP64 moments [G][R][6]; returns DGD_EUNSTABLE (moments filled anyway) on a
 // non-finite value or mass drift beyond the precision's tolerance.
 int run_moments(dgd_run* run, double* out, std::string* why) {
+  Range range("dgd:moments");
   const RunTarget& t = run->t;
   const Shape shr = reduce_shape(t.E);
   launch_moments(t.prec == DGD_FP64 ? 0 : 1, t.np, run->U, t.elem, t.E, t.W, run->d_x0,
@@ -980,8 +1055,10 @@ size_t batch_group_bytes(const dgd_batch::Group& grp, const dgd_batch* b, RunTar
 // and (if non-NULL) the moments [R][nd][6]; stops at the first Delta whose
 // moments fail the mass check and reports it.
 void solve_deltas(dgd_run* run, const std::vector<std::pair<int64_t, double>>& sched, int n_points,
-                  int n_deltas, double* sigma_out, double* moments_out) {
+                  int n_deltas, double* sigma_out, double* moments_out,
+                  std::vector<double>* all = nullptr) {
   std::vector<double> mom((size_t)n_points * 6);
+  if (all) all->assign((size_t)n_points * n_deltas * 6, 0.0);
   std::string why;
   for (int k = 0; k < n_deltas; ++k) {
     run_advance(run, sched[k].first, sched[k].second);
@@ -993,6 +1070,7 @@ void solve_deltas(dgd_run* run, const std::vector<std::pair<int64_t, double>>& s
       s[1] = m[4] / m[0];
       s[2] = m[5] / m[0];
       if (moments_out) std::memcpy(&moments_out[((size_t)r * n_deltas + k) * 6], m, 6 * sizeof(double));
+      if (all) std::memcpy(&(*all)[((size_t)r * n_deltas + k) * 6], m, 6 * sizeof(double));
     }
     if (mrc) fail(mrc, why);
   }
@@ -1289,10 +1367,13 @@ static int build_operator(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, 
       if (dt_max_ms > 0) {
         op->dt_nom = std::min(dt_formula, dt_max_ms);
         op->lambda_max = 0;
+        op->dt_rule = dt_formula <= dt_max_ms ? "formula" : "caller";
       } else {
         const double lam = power_lambda(op, 400) * D_um2_per_ms / (h * h);
         op->lambda_max = lam;
-        op->dt_nom = std::min(dt_formula, 0.9 * rk3_limit() / (1.05 * lam));
+        const double dt_stab = 0.9 * rk3_limit() / (1.05 * lam);
+        op->dt_nom = std::min(dt_formula, dt_stab);
+        op->dt_rule = dt_formula <= dt_stab ? "formula" : "stability";
       }
     } catch (...) {
       dgd_operator_destroy(op);
@@ -1579,12 +1660,21 @@ int dgd_eap_solve(dgd_op* op, const double* points, int32_t n_points, double sig
     return DGD_OK;
   });
   if (rc) return rc;
+  Range range("dgd:eap_solve");
+  const auto t0 = std::chrono::steady_clock::now();
   rc = dgd_run_create(op, points, n_points, sigma0_um, d_ws, ws_bytes, hip_stream, &run);
   if (rc) return rc;
+  std::vector<double> all;
   rc = guarded([&]() -> int {
-    solve_deltas(run, sched, n_points, n_deltas, sigma_out, moments_out);
+    solve_deltas(run, sched, n_points, n_deltas, sigma_out, moments_out, &all);
     return DGD_OK;
   });
+  int64_t steps = 0;
+  for (const auto& s : sched) steps += s.first;
+  const int64_t E = op->mesh->host.n_elements();
+  log_run("dgd_eap_solve", op, 1, E, n_points, deltas_ms, n_deltas, steps,
+          (double)E * op->ref.np * n_points * steps, seconds_since(t0), rc, all.data(),
+          kKindName[run->kind]);
   dgd_run_destroy(run);
   return rc;
 }
@@ -1615,7 +1705,23 @@ int dgd_eap_solve_noalloc(dgd_op* op, const double* points, int32_t n_points, do
     check_axon_cells(op, points, n_points);
     run = run_create(t, points, n_points, sigma0_um, scratch_address(dev), kScratchBytes,
                      hip_stream, true);
-    solve_deltas(run, sched, n_points, n_deltas, sigma_out, moments_out);
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<double> all;
+    int status = DGD_OK;
+    std::string why;
+    try {
+      solve_deltas(run, sched, n_points, n_deltas, sigma_out, moments_out, &all);
+    } catch (const Error& e) {
+      status = e.code;
+      why = e.msg;
+    }
+    int64_t steps = 0;
+    for (const auto& s : sched) steps += s.first;
+    const int64_t E = op->mesh->host.n_elements();
+    log_run("dgd_eap_solve_noalloc", op, 1, E, n_points, deltas_ms, n_deltas, steps,
+            (double)E * op->ref.np * n_points * steps, seconds_since(t0), status, all.data(),
+            kKindName[run->kind]);
+    if (status) fail(status, why);
     return DGD_OK;
   });
   run_destroy(run);
@@ -1913,14 +2019,23 @@ int dgd_eap_solve_batch(dgd_op* const* ops, int32_t n_geoms, const double* point
     return DGD_OK;
   });
   if (rc) return rc;
+  Range range("dgd:eap_solve_batch");
+  const auto t0 = std::chrono::steady_clock::now();
   rc = dgd_batch_create(ops, n_geoms, points, n_points, sigma0_um, d_ws, ws_bytes, hip_stream, &b);
   if (rc) return rc;
+  std::vector<double> all((size_t)n_geoms * n_points * n_deltas * 6, 0.0);
+  int64_t steps_max = 0;
+  double updates = 0;
   rc = guarded([&]() -> int {
     const int R = n_points;
     int status = DGD_OK;
     std::string why;
     for (auto& grp : b->groups) {
       const auto sched = schedule(deltas_ms, n_deltas, grp.dt);
+      int64_t gsteps = 0;
+      for (const auto& s : sched) gsteps += s.first;
+      steps_max = std::max(steps_max, gsteps);
+      updates += (double)grp.dof * R * gsteps;
       std::vector<double> m((size_t)grp.geoms.size() * R * 6);
       for (int k = 0; k < n_deltas; ++k) {
         run_advance(grp.run, sched[k].first, sched[k].second);
@@ -1937,6 +2052,7 @@ int dgd_eap_solve_batch(dgd_op* const* ops, int32_t n_geoms, const double* point
             if (moments_out)
               std::memcpy(&moments_out[(((size_t)g * R + r) * n_deltas + k) * 6], mm,
                           6 * sizeof(double));
+            std::memcpy(&all[(((size_t)g * R + r) * n_deltas + k) * 6], mm, 6 * sizeof(double));
           }
         }
         if (mrc && !status) {
@@ -1948,6 +2064,10 @@ int dgd_eap_solve_batch(dgd_op* const* ops, int32_t n_geoms, const double* point
     if (status) fail(status, why);
     return DGD_OK;
   });
+  int64_t elements = 0;
+  for (int g = 0; g < n_geoms; ++g) elements += ops[g]->mesh->host.n_elements();
+  log_run("dgd_eap_solve_batch", ops[0], n_geoms, elements, n_geoms * n_points, deltas_ms, n_deltas,
+          steps_max, updates, seconds_since(t0), rc, all.data(), "batched");
   dgd_batch_destroy(b);
   return rc;
 }

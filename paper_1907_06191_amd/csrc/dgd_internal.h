@@ -110,6 +110,7 @@ struct dgd_op {
   int precision = DGD_FP64;
   double D = 0;
   double dt_nom = 0, lambda_max = 0;
+  const char* dt_rule = "";   // which term set dt_nom: "formula", "stability" or "caller"
   void* d_S = nullptr;    // [2][8][np][np] FP64
   void* d_N = nullptr;    // [2][3][np][np] FP64
   void* d_F = nullptr;    // [2][3][np][np] FP64 self-face blocks (packed stage kernel)

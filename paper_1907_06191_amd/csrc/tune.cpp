@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <mutex>
 #include <sstream>
 #include <vector>
@@ -49,6 +51,16 @@ struct Events {
   }
 };
 
+// DGD_TUNE_CACHE names a file holding the shape table in the text form of
+// tune_export: read once before the first lookup (a missing or malformed
+// file is ignored) and rewritten after every newly tuned key.
+const char* cache_path() {
+  const char* p = std::getenv("DGD_TUNE_CACHE");
+  return p && *p ? p : nullptr;
+}
+
+void load_cache_once();
+
 bool valid(const TuneParams& p) {
   return (p.epw == 1 || p.epw == 2 || p.epw == 4 || p.epw == 8) &&
          (p.waves == 1 || p.waves == 2 || p.waves == 4) && (p.remap == 0 || p.remap == 1) &&
@@ -66,6 +78,7 @@ std::string tune_key(int np, int prec, const char* kernel, int R, int64_t E) {
 }
 
 bool tune_find(const std::string& key, TuneParams* out) {
+  load_cache_once();
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_table.find(key);
   if (it == g_table.end()) return false;
@@ -153,8 +166,18 @@ TuneParams tune_stage(const std::string& key, int64_t units, int prec, int64_t n
   std::sort(cand.begin(), cand.begin() + top,
             [](const TuneParams& x, const TuneParams& y) { return x.ms < y.ms; });
   const TuneParams best = cand[0];
-  std::lock_guard<std::mutex> lk(g_mu);
-  g_table[key] = best;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table[key] = best;
+  }
+  if (const char* path = cache_path()) {
+    const std::string text = tune_export();
+    const std::string tmp = std::string(path) + ".tmp";
+    if (std::FILE* f = std::fopen(tmp.c_str(), "w")) {
+      const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+      if (std::fclose(f) == 0 && ok) std::rename(tmp.c_str(), path);
+    }
+  }
   return best;
 }
 
@@ -185,6 +208,28 @@ int tune_import(const std::string& text) {
   for (auto& r : rows) g_table[r.first] = r.second;
   return (int)rows.size();
 }
+
+namespace {
+void load_cache_once() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const char* path = cache_path();
+    if (!path) return;
+    std::FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
+    std::fclose(f);
+    try {
+      tune_import(text);
+    } catch (const Error&) {
+      // a malformed cache is ignored: the shapes are tuned again
+    }
+  });
+}
+}  // namespace
 
 void tune_clear() {
   std::lock_guard<std::mutex> lk(g_mu);

@@ -359,12 +359,13 @@ def test_p3_mfma_operator_extraction(dgd):
 def test_p3_mfma_solve_matches_valu_and_oracle(dgd):
     """P3 on a dense packing, 16 start points: the matrix-core path agrees
     with the FP64-arithmetic VALU path and with the oracle (1e-4), and keeps
-    the mass to 5e-6.
+    the mass to 2.5e-6.
 
     The FP32 state is stored with stochastic rounding, so its mass error is
-    a zero-mean random walk: per stage about sqrt(#values) x (weight x 0.3
-    ulp) ~ 1e-8 here (10^4 values near 1, weights ~ 2e-3), ~1e-6 after the
-    15k steps of this run.  Round-to-nearest storage drifts linearly
+    a zero-mean random walk: per stage at most sqrt(#values) x (weight x 0.4
+    ulp) ~ 1e-8 here (10^4 values near 1, weights ~ 2e-3), at most ~2e-6
+    after the 45k stages of this run, and measured 7.4e-7 (max over the 16
+    columns and both Delta).  Round-to-nearest storage drifts linearly
     instead (2e-5 over the same run)."""
     g, pts = _small_dense_case(nrhs=16, N=32, seed=21)
     deltas = [0.05, 0.1]
@@ -386,7 +387,7 @@ def test_p3_mfma_solve_matches_valu_and_oracle(dgd):
     drift = np.abs(mom_m[..., 0] - 1).max()
     say(f"  mfma vs oracle {e_ref:.2e}, vs valu {e_valu:.2e}, |M0-1| {drift:.2e}")
     assert e_ref < 1e-4 and e_valu < 1e-4
-    assert drift < 5e-6
+    assert drift < 2.5e-6
 
 
 @pytest.mark.parametrize("p", [1, 2, 3])
