@@ -213,7 +213,9 @@ int dgd_run_create(dgd_op* op, const double* points, int32_t n_points, double si
                    void* d_ws, size_t ws_bytes, void* hip_stream, dgd_run** out);
 
 /* Advance every column by n_steps SSP-RK3 steps of dt_ms (asynchronous on
- * the run's stream; steps are replayed from captured HIP graphs). */
+ * the run's stream; steps are replayed from captured HIP graphs: the first
+ * advance with a given dt captures graphs of graph_steps steps and of every
+ * power of two up to it, so any later count with that dt only replays). */
 int dgd_run_advance(dgd_run* run, int64_t n_steps, double dt_ms);
 
 /* FP64 moments about each start point, host [n_points][6] =
@@ -417,7 +419,7 @@ void dgd_surrogate_destroy(dgd_surrogate* s);
 
 /* Runtime options (process-wide; read when a run is created or advanced):
  *   "graphs"       1 = replay steps from captured HIP graphs, 0 = plain launches
- *   "graph_steps"  steps captured per graph, 1..4096
+ *   "graph_steps"  steps of the largest captured graph, 1..4096
  *   "stage_epw"    elements walked by each wave of the stage kernel, 1..256
  *   "stage_waves"  waves per workgroup of the stage kernel, 1..4
  *   "xcd_remap"    1 = each XCD sweeps one contiguous band of elements

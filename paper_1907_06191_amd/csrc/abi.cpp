@@ -820,14 +820,22 @@ void run_advance(dgd_run* run, int64_t n_steps, double dt) {
   if (n_steps < 0) fail(DGD_EINVAL, "n_steps must be >= 0");
   if (!(dt > 0) || !std::isfinite(dt)) fail(DGD_EINVAL, "dt must be positive");
   if (n_steps == 0) return;
-  const int64_t G = g_opt.graph_steps;
   int64_t left = n_steps;
-  if (g_opt.graphs && !run->eager && left >= G) {
-    hipGraphExec_t ex = step_graph(run, G, dt);
-    while (left >= G) {
-      DGD_HIP_CHECK(hipGraphLaunch(ex, run->stream));
-      left -= G;
-    }
+  if (g_opt.graphs && !run->eager) {
+    // Graphs of graph_steps steps and of every power of two up to it, all
+    // captured on the first advance with this dt: any step count then runs as
+    // replays (whole graphs, then the remainder's binary digits, each below
+    // the largest power of two not above graph_steps), and a later advance
+    // with the same dt, of whatever length, captures nothing.
+    const int64_t G = g_opt.graph_steps;
+    int64_t top = 1;
+    while (2 * top <= G) top *= 2;
+    std::vector<std::pair<int64_t, hipGraphExec_t>> ladder;
+    ladder.emplace_back(G, step_graph(run, G, dt));
+    for (int64_t s = top; s >= 1; s /= 2)
+      if (s != G) ladder.emplace_back(s, step_graph(run, s, dt));
+    for (const auto& g : ladder)
+      for (; left >= g.first; left -= g.first) DGD_HIP_CHECK(hipGraphLaunch(g.second, run->stream));
   }
   run_stage_steps(run, left, dt);
   DGD_HIP_CHECK(hipGetLastError());

@@ -234,6 +234,17 @@ def test_determinism_graphs_and_checkpoint(dgd):
         assert np.array_equal(x, z)
     assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[0], sc[0])
     assert sa[1] == 201
+    # a largest graph that is no power of two (graphs of 24, 16, 8, 4, 2, 1
+    # steps), and counts below it, replay bitwise like plain launches
+    dgd.dgd_set_option("graph_steps", 24)
+    try:
+        e, se = run([100, 37, 64])
+        f, _ = run([5, 3, 19, 1, 7])
+        h, _ = run([5, 3, 19, 1, 7], graphs=False)
+    finally:
+        dgd.dgd_set_option("graph_steps", 32)
+    assert all(np.array_equal(x, y) for x, y in zip(a, e)) and np.array_equal(sa[0], se[0])
+    assert all(np.array_equal(x, y) for x, y in zip(f, h))
     # checkpoint (state and step count) after 137 steps, resume for 64
     _, s137 = run([100, 37])
     d, sd = run([64], restore=s137)
