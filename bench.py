@@ -165,7 +165,8 @@ def plain(args):
     log(f"geometry: {g.disks.shape[0]} disks in {time.time() - t0:.1f}s")
     mesh = dgd.Mesh(g.L, g.N, g.disks)
     info = mesh.info()
-    prec = dgd.DGD_FP64 if c["precision"] == "fp64" else dgd.DGD_FP32
+    prec_name = args.precision or c["precision"]
+    prec = {"fp64": dgd.DGD_FP64, "fp32": dgd.DGD_FP32, "bf16x3": dgd.DGD_BF16X3}[prec_name]
     t0 = time.time()
     op = dgd.Operator(mesh, p, c["D"], c["eta"], prec)
     dt, lam = dgd.dgd_operator_dt(op.handle)
@@ -193,10 +194,13 @@ def plain(args):
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     kind, shape = dgd.dgd_run_kernel(run.handle)
     ts = "double" if sbytes == 8 else "float"
-    kernel = {"mfma": "k_stage_p3_mfma", "packed": f"k_stage_packed<{ts},{npn},{4 if R <= 16 else 2}>",
+    kernel = {"mfma": "k_stage_p3_mfma<false>", "mfma_bf16x3": "k_stage_p3_mfma<true>",
+              "packed": f"k_stage_packed<{ts},{npn},{4 if R <= 16 else 2}>",
               "valu": f"k_stage<{ts},{npn}>"}[kind]
-    dtype = ("f32 MFMA contraction + f64 mass correction, f32 state" if kind == "mfma" else
-             ("f64 arithmetic, f32 state" if sbytes == 4 else "f64"))
+    dtype = {"mfma": "f32 MFMA contraction + f64 mass correction, f32 state",
+             "mfma_bf16x3": "bf16 hi/lo split MFMA contraction (3 products, f32 accumulate) "
+                            "+ f64 mass correction, f32 state"}.get(
+        kind, "f64 arithmetic, f32 state" if sbytes == 4 else "f64")
     out = base_record(args, value, ms_per_step, dtype, {
         "workload": f"{args.workload}: plain solve, {g.N}x{g.N} grid on [0,{g.L:g}]^2 um, "
                     f"phi={c['phi'] if c['phi'] is not None else str(c['n_disks']) + ' disks'}, "
@@ -216,14 +220,24 @@ def plain(args):
         "bytes_per_launch": bytes_per_launch, "launch_ms": round(launch_ms, 5), "launch_shape": shape,
         "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated), "
                         "null unless measured on this kernel source and launch shape"}
-    if kind == "mfma":
-        # useful flops of the contraction: the 10 x 40 stencil matrix times
-        # the 40 gathered values, per element and right-hand side
-        flops = 2.0 * 10 * 40 * info["n_active"] * R
-        out["roofline_mfma"] = {"bound": "mfma", "achieved": round(flops / (launch_ms * 1e-3) / 1e12, 3),
-                                "peak": 157.3, "unit": "TFLOP/s",
-                                "frac": round(flops / (launch_ms * 1e-3) / 1e12 / 157.3, 4),
-                                "flops_per_launch": flops, "dtype": "fp32 MFMA (v_mfma_f32_16x16x4_f32)"}
+    if kind in ("mfma", "mfma_bf16x3"):
+        # the method's flops per element and right-hand side: the 10 x 10
+        # self block and one 10 x 10 block per present face (2 Np^2 (1 + faces));
+        # interior faces count twice, once from each side.  The BF16 split
+        # does the contraction three times (A_mid x_hi, A_hi x_lo, A_hi x_hi).
+        method = 2.0 * npn * npn * (info["n_active"] + 2 * info["n_faces"]) * R
+        nprod = 3 if kind == "mfma_bf16x3" else 1
+        peak = 2500.0 if kind == "mfma_bf16x3" else 157.3
+        issued = (2 * 3 * 16 * 16 * 32 * 2 if nprod == 3 else 10 * 16 * 16 * 4 * 2) * info["n_active"] * R / 16
+        rate = method * nprod / (launch_ms * 1e-3) / 1e12
+        out["roofline_mfma"] = {
+            "bound": "mfma", "achieved": round(rate, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(rate / peak, 5), "flops_per_launch": method * nprod,
+            "issued_flops_per_launch": issued,
+            "dtype": ("bf16 MFMA (v_mfma_f32_16x16x32_bf16), 3 split products" if nprod == 3 else
+                      "fp32 MFMA (v_mfma_f32_16x16x4_f32)"),
+            "note": "method flops 2 Np^2 (1 + present faces) per element and right-hand side, "
+                    "times the products the split needs; issued counts the padded 16 x 16 tiles"}
     run.close()
     if args.expm:
         torch.cuda.synchronize()
@@ -360,6 +374,9 @@ def main():
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
                     help="skip the mixed-form leg (the paper's own formulation on all pixels)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16x3"],
+                    help="operator precision (default: the workload's); bf16x3 = P3 stages as "
+                         "BF16 hi/lo split products on matrix cores")
     ap.add_argument("--p3-mfma", type=int, default=2, choices=[0, 1, 2],
                     help="P3 FP32 stage kernel: 0 VALU, 1 matrix cores, 2 the faster (tuned)")
     ap.add_argument("--tune-file", default=None,

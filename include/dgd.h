@@ -50,7 +50,7 @@ extern "C" {
 /* Precision of operator and state.  Moments are always reduced in FP64. */
 #define DGD_FP64 0
 #define DGD_FP32 1
-#define DGD_BF16X3 2        /* reserved (BF16 hi/lo split products): rejected with EINVAL */
+#define DGD_BF16X3 2        /* FP32 state, P3 stages as BF16 hi/lo split products on matrix cores */
 
 /* Condition on the edges of the square (dgd_operator_build_outer). */
 #define DGD_OUTER_REFLECT 0 /* zero flux */
@@ -111,7 +111,15 @@ void dgd_mesh_destroy(dgd_mesh* mesh);
  *   precision: DGD_FP64 or DGD_FP32 (state precision; with DGD_FP32 and a
  *     right-hand-side count that is a multiple of 16, P3 stages may run on
  *     matrix cores: option "p3_mfma", by default only where the autotuner
- *     timed them faster than the FP64 vector kernel);
+ *     timed them faster than the FP64 vector kernel), or DGD_BF16X3 (p = 3,
+ *     zero-flux walls: FP32 state, every RK3 stage contracts the stacked
+ *     element stencil on matrix cores as BF16 hi/lo split products --
+ *     operator in two BF16 terms, state differences in two, three products
+ *     accumulated in FP32, error below about 2^-16 of each product -- with
+ *     the FP64 per-element mass correction (section 3.1 remark on p <= 3);
+ *     runs need a multiple of 16 right-hand sides (EINVAL otherwise), the
+ *     Chebyshev exponential runs its FP64 vector path, and batches refuse
+ *     such operators);
  *   dt_max_ms > 0: nominal step = min(0.1 h^2 / (D (p+1)^2), dt_max_ms);
  *   dt_max_ms <= 0: nominal step = min(0.1 h^2 / (D (p+1)^2), 0.9 X / b),
  *     X = 2.5127... the real stability limit of SSP-RK3 and
@@ -260,7 +268,8 @@ int dgd_run_set_step_count(dgd_run* run, int64_t steps);
 
 /* The stage kernel and launch shape the run uses: kernel 0 = one element
  * and up to 64 right-hand sides per wave, 1 = several elements per wave
- * (at most 32 right-hand sides), 2 = P3 on matrix cores; shape_out
+ * (at most 32 right-hand sides), 2 = P3 on matrix cores (FP32 products),
+ * 3 = P3 on matrix cores (BF16 hi/lo split products, DGD_BF16X3); shape_out
  * (nullable) [4] = (elements per wave, waves per workgroup, XCD band order,
  * workgroups launched).  Errors: EINVAL. */
 int dgd_run_kernel(const dgd_run* run, int32_t* kernel_out, int64_t* shape_out);

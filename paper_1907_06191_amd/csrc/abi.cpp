@@ -197,6 +197,7 @@ RunTarget plain_target(const dgd_op* op) {
   t.G = 1;
   t.nblk_red = reduce_shape(t.E).blocks;
   t.Atab = op->d_Atab;
+  t.Atab_bf = op->bf16x3 ? op->d_Atab_bf : nullptr;
   t.Ctab = op->d_Ctab;
   t.Wtab = op->d_Wtab;
   t.wsum = op->wsum;
@@ -221,9 +222,10 @@ bool mfma_possible(const RunTarget& t, int R) {
 
 // Stage kernels: one element and up to 64 right-hand sides per wave
 // (VALU); for R <= 32 several elements per wave (packed); P3 FP32 with R a
-// multiple of 16 on matrix cores (mfma).
-enum StageKind { kValu = 0, kPacked = 1, kMfma = 2 };
-const char* const kKindName[3] = {"valu", "packed", "mfma"};
+// multiple of 16 on matrix cores, FP32 products (mfma) or BF16 hi/lo split
+// products (mfma_bf16x3, the DGD_BF16X3 precision).
+enum StageKind { kValu = 0, kPacked = 1, kMfma = 2, kMfmaBf16 = 3 };
+const char* const kKindName[4] = {"valu", "packed", "mfma", "mfma_bf16x3"};
 
 // The VALU kernel for (t, R): packed when R <= 32.
 StageKind valu_kind(const RunTarget& t, int R) {
@@ -263,6 +265,12 @@ std::string kind_key(const RunTarget& t, int R, StageKind k) {
 // ("p3_mfma" 1), else the faster of the tuned kinds when both are in the
 // table ("p3_mfma" 2, autotuning on), else the VALU kernel.
 StageKind stage_kind(const RunTarget& t, int R) {
+  if (t.Atab_bf) {
+    if (!mfma_possible(t, R))
+      fail(DGD_EINVAL, "DGD_BF16X3 runs P3 stages on matrix cores in blocks of 16 right-hand "
+                       "sides: the count must be a multiple of 16 (and E * 10 * R < 2^31)");
+    return kMfmaBf16;
+  }
   const StageKind v = valu_kind(t, R);
   if (!mfma_possible(t, R) || g_opt.p3_mfma == 0) return v;
   if (g_opt.p3_mfma == 1) return kMfma;
@@ -295,8 +303,10 @@ void stage(const RunTarget& t, StageKind kind, const Shape& sh, const void* us, 
   }
   switch (kind) {
     case kMfma:
-      launch_stage_p3_mfma(us, ub, out, t.elem, t.E, t.Atab, t.Ctab, t.Wtab, t.wsum, mode, cb, cg,
-                           R, sh, st, step, stage_id);
+    case kMfmaBf16:
+      launch_stage_p3_mfma(kind == kMfmaBf16, us, ub, out, t.elem, t.E,
+                           kind == kMfmaBf16 ? (const void*)t.Atab_bf : (const void*)t.Atab,
+                           t.Ctab, t.Wtab, t.wsum, mode, cb, cg, R, sh, st, step, stage_id);
       break;
     case kPacked:
       launch_stage_packed(t.prec == DGD_FP64 ? 0 : 1, t.np, packed_group(R), us, ub, out, t.elem,
@@ -328,6 +338,7 @@ StageKind tune_target(const RunTarget& t, int R, void* a, void* b, const void* b
   std::vector<StageKind> kinds{valu_kind(t, R)};
   if (mfma_possible(t, R) && g_opt.p3_mfma != 0) kinds.push_back(kMfma);
   if (g_opt.p3_mfma == 1 && mfma_possible(t, R)) kinds = {kMfma};
+  if (t.Atab_bf) kinds = {stage_kind(t, R)};
   for (StageKind k : kinds) {
     TuneParams p;
     if (force || !tune_find(kind_key(t, R, k), &p)) tune_kind(t, R, k, a, b, base, st);
@@ -370,15 +381,35 @@ void build_mixed_tables(dgd_op* op, const double* disks, int n_disks) {
   op->form = 1;
 }
 
+// FP32 and BF16 round to nearest even (finite values)
+static uint16_t bf16_rne(double x) {
+  const float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static double bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
 // Tables of the P3 matrix-core kernel: for class (o, mask) the stacked
 // stencil matrix A = [S | N_0 | N_1 | N_2] (10 x 40, missing faces zero,
 // rows 10..15 zero), in FP32 and in the lane order of v_mfma_f32_16x16x4
 // (lane l, step s holds A[l % 16][4 s + l / 16], stored [class][s][lane]); C = w^T A in FP64 with
-// w the row sums of the reference mass matrix; W = w padded to 16.
+// w the row sums of the reference mass matrix; W = w padded to 16.  With
+// DGD_BF16X3 also A = A_hi + A_mid in BF16 (A_hi = A rounded, A_mid = the
+// remainder rounded) in the lane order of v_mfma_f32_16x16x32_bf16 as the
+// kernel uses it: lane l, step h, slot j < 5 holds A[l % 16][20 h + 5 (l / 16) + j],
+// slots 5..7 zero, stored [class][h][hi, mid][lane][slot].
 void build_p3_tables(dgd_op* op) {
   const RefElem& R = op->ref;
   const int np = R.np;  // 10
   std::vector<float> At(16 * 64 * 10, 0.f);
+  std::vector<uint16_t> Ab(op->bf16x3 ? 16 * 2 * 2 * 64 * 8 : 0, 0);
   std::vector<double> Ct(16 * 40, 0.0), Wt(2 * 16, 0.0);
   double wsum = 0;
   for (int o = 0; o < 2; ++o) {
@@ -406,9 +437,20 @@ void build_p3_tables(dgd_op* op) {
       // contiguous 256-byte row
       for (int s = 0; s < 10; ++s)
         for (int l = 0; l < 64; ++l) At[(cls * 10 + s) * 64 + l] = (float)A[(l % 16) * 40 + 4 * s + l / 16];
+      if (!op->bf16x3) continue;
+      for (int h = 0; h < 2; ++h)
+        for (int l = 0; l < 64; ++l)
+          for (int j = 0; j < 5; ++j) {
+            const double a = A[(l % 16) * 40 + 20 * h + 5 * (l / 16) + j];
+            const uint16_t hi = bf16_rne(a);
+            const uint16_t mid = bf16_rne(a - bf16_value(hi));
+            Ab[((((size_t)cls * 2 + h) * 2 + 0) * 64 + l) * 8 + j] = hi;
+            Ab[((((size_t)cls * 2 + h) * 2 + 1) * 64 + l) * 8 + j] = mid;
+          }
     }
   }
   op->d_Atab = (float*)upload(At);
+  if (op->bf16x3) op->d_Atab_bf = (uint16_t*)upload(Ab);
   op->d_Ctab = (double*)upload(Ct);
   op->d_Wtab = (double*)upload(Wt);
   op->wsum = wsum;
@@ -555,7 +597,8 @@ void log_run(const char* entry, const dgd_op* op, int n_geoms, int64_t elements,
   std::fprintf(f, "{\"entry\": \"%s\", \"p\": %d, \"precision\": \"%s\", \"form\": \"%s\", "
                "\"outer\": \"%s\", \"geometries\": %d, \"elements\": %lld, \"n_points\": %d, "
                "\"deltas_ms\": [",
-               entry, op->ref.p, op->precision == DGD_FP64 ? "fp64" : "fp32",
+               entry, op->ref.p,
+               op->bf16x3 ? "bf16x3" : (op->precision == DGD_FP64 ? "fp64" : "fp32"),
                op->form == 1 ? "mixed" : "primal", op->outer == DGD_OUTER_ABSORB ? "absorb" : "reflect",
                n_geoms, (long long)elements, n_points);
   for (int k = 0; k < n_deltas; ++k) std::fprintf(f, "%s%.17g", k ? ", " : "", deltas[k]);
@@ -1336,15 +1379,19 @@ static int build_operator(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, 
     if (p < 1 || p > 3) fail(DGD_EINVAL, "p must be 1, 2 or 3");
     if (!(D_um2_per_ms > 0) || !std::isfinite(D_um2_per_ms)) fail(DGD_EINVAL, "D must be positive");
     if (!(eta > 0) || !std::isfinite(eta)) fail(DGD_EINVAL, "eta must be positive");
-    if (precision != DGD_FP64 && precision != DGD_FP32)
-      fail(DGD_EINVAL, "precision must be DGD_FP64 or DGD_FP32");
+    if (precision != DGD_FP64 && precision != DGD_FP32 && precision != DGD_BF16X3)
+      fail(DGD_EINVAL, "precision must be DGD_FP64, DGD_FP32 or DGD_BF16X3");
+    if (precision == DGD_BF16X3 && (p != 3 || form != 0 || outer != DGD_OUTER_REFLECT))
+      fail(DGD_EINVAL, "DGD_BF16X3 (BF16 hi/lo split products on matrix cores) is the P3 "
+                       "primal operator with zero-flux walls only");
     if (!std::isfinite(dt_max_ms)) fail(DGD_EINVAL, "dt_max_ms must be finite");
     if (mesh->host.n_elements() == 0) fail(DGD_EINVAL, "mesh has no active element");
     auto* op = new dgd_op();
     try {
       ensure_mesh_on_device(mesh);
       op->mesh = mesh;
-      op->precision = precision;
+      op->precision = precision == DGD_BF16X3 ? DGD_FP32 : precision;   // state precision
+      op->bf16x3 = precision == DGD_BF16X3;
       op->D = D_um2_per_ms;
       op->ref = build_ref_elem(p, eta);
       const RefElem& R = op->ref;
@@ -1366,7 +1413,7 @@ static int build_operator(const dgd_mesh* mesh, int32_t p, double D_um2_per_ms, 
       for (size_t k = 0; k < Mp.size(); ++k) Mp[k] = R.Mass[k] * h * h;
       op->d_W = (double*)upload(Wp);
       op->d_Mass = (double*)upload(Mp);
-      if (p == 3 && precision == DGD_FP32 && form == 0) build_p3_tables(op);
+      if (p == 3 && op->precision == DGD_FP32 && form == 0) build_p3_tables(op);
       if (form == 1) build_mixed_tables(op, disks, n_disks);
       op->quad = build_ic_quadrature(R, kQuadN);
       op->nq = kQuadN * kQuadN;
@@ -1429,7 +1476,7 @@ int dgd_operator_info(const dgd_op* op, int32_t* np, double* nodes, int32_t* pre
     if (!op) fail(DGD_EINVAL, "op is NULL");
     if (np) *np = op->ref.np;
     if (nodes) std::memcpy(nodes, op->ref.nodes.data(), op->ref.nodes.size() * sizeof(double));
-    if (precision) *precision = op->precision;
+    if (precision) *precision = op->bf16x3 ? DGD_BF16X3 : op->precision;
     return DGD_OK;
   });
 }
@@ -1492,6 +1539,7 @@ void dgd_operator_destroy(dgd_op* op) {
   (void)hipFree(op->d_Mass);
   (void)hipFree(op->d_quad);
   (void)hipFree(op->d_Atab);
+  (void)hipFree(op->d_Atab_bf);
   (void)hipFree(op->d_Ctab);
   (void)hipFree(op->d_Wtab);
   delete op;
@@ -1795,6 +1843,7 @@ int dgd_eap_solve_expm(dgd_op* op, const double* points, int32_t n_points, doubl
     RunTarget t = plain_target(op);
     t.prec = DGD_FP64;           // the recurrence runs on an FP64 state
     t.Atab = nullptr;
+    t.Atab_bf = nullptr;
     run = run_create(t, points, n_points, sigma0_um, nullptr, 0, nullptr);
     const int64_t n = t.E * t.np * (int64_t)n_points;
     DGD_HIP_CHECK(hipMalloc(&buf, (size_t)n * sizeof(double)));
@@ -1877,6 +1926,7 @@ int dgd_batch_create(dgd_op* const* ops, int32_t n_geoms, const double* points, 
     if (!(sigma0_um >= 0) || !std::isfinite(sigma0_um)) fail(DGD_EINVAL, "sigma0 must be >= 0");
     for (int g = 0; g < n_geoms; ++g) {
       if (!ops[g]) fail(DGD_EINVAL, "NULL operator");
+      if (ops[g]->bf16x3) fail(DGD_EINVAL, "batched solves take DGD_FP64 or DGD_FP32 operators");
       const dgd_op* a = ops[g];
       const dgd_op* z = ops[0];
       if (a->mesh->host.h != z->mesh->host.h || a->D != z->D || a->ref.eta != z->ref.eta ||

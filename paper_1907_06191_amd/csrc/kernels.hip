@@ -563,30 +563,73 @@ __global__ void __launch_bounds__(256) k_mixed_div(const TS* __restrict__ q, con
 // P3 stage on matrix cores (FP32 state, R a multiple of 16).  For element K
 // of class (o, mask) the contraction over the stacked stencil
 //   L(u)_K = [S_{o,mask} | N_{o,0} | N_{o,1} | N_{o,2}] (u_stencil - c)
-// is a (10 x 40) x (40 x 16) product per block of 16 right-hand sides, run
-// as ten v_mfma_f32_16x16x4_f32 steps (K = 40 = 10 x 4 exactly; rows 10..15
-// of A are zero; a missing face has zero columns).  Lane l of a step holds
-// A[m = l % 16][k = 4 s + l / 16] and B[k = 4 s + l / 16][n = l % 16] and
-// receives D[m = 4 (l / 16) + i][n = l % 16], i < 4.
+// (rows 10..15 of the stacked matrix A are zero; a missing face has zero
+// columns) is a (16 x 40) x (40 x 16) product per block of 16 right-hand
+// sides, in one of two forms:
+//  * FP32 (BF false): ten v_mfma_f32_16x16x4_f32 steps (K = 40 = 10 x 4
+//    exactly).  Lane l of step s holds A[m = l % 16][k = 4 s + l / 16] and
+//    B[k = 4 s + l / 16][n = l % 16].
+//  * BF16 hi/lo split (BF true): two v_mfma_f32_16x16x32_bf16 steps h, each
+//    over 20 stencil rows padded to 32: lane l of step h holds eight values,
+//    slot j < 5 of stencil row k = 20 h + 5 (l / 16) + j and slots 5..7 zero,
+//    for row m = l % 16 of A and column n = l % 16 of B (the operand layout
+//    only has to give a lane's slot j the same k in A and in B, which the
+//    instruction does).  A is split on the host into A_hi + A_mid, both BF16
+//    (16 significant bits together); each value x = u - c is split here into
+//    x_hi = bf16(x) and x_lo = bf16(x - x_hi) (error below 2^-17 |x|), and
+//    the step accumulates A_mid x_hi + A_hi x_lo + A_hi x_hi in FP32 (the
+//    dropped A_mid x_lo is below 2^-18).  Six matrix instructions per block
+//    of 16 right-hand sides instead of ten at twice the cost each.
+// Either way lane l receives D[m = 4 (l / 16) + i][n = l % 16], i < 4.
 //
 // A wave covers 64 right-hand sides of an element (blockIdx.y selects which
 // 64).  Lane (q, n) = (l / 16, l % 16) loads the four consecutive columns
-// 4n .. 4n+3 of stencil row 4 s + q as one 16-byte load, so each step's
-// loads are four whole 256-byte rows; the four 16-column blocks are
+// 4n .. 4n+3 of each of its ten stencil rows as one 16-byte load, so the
+// wave's loads are whole 256-byte rows; the four 16-column blocks are
 // t = 0..3 with block t holding columns {4n + t}: the t-th component of
 // every lane's load is exactly that block's B operand, and the four blocks'
 // results for a row are again four consecutive columns, stored as one
 // 16-byte store.
 //
-// FP32 products lose mass systematically over 10^6 steps, so each column's
-// result is corrected by a constant so that its mass w^T L(u) equals the
-// FP64 sum of the face fluxes, Phi = C_{o,mask} . u_stencil, with the flux
-// coefficients C = w^T [S | N...] (w = reference mass-matrix row sums).
-// Atab: [16 classes][10 steps][64 lanes] float; Ctab: [16][40] double;
+// Rounded products lose mass systematically over 10^6 steps, so each
+// column's result is corrected by a constant so that its mass w^T L(u)
+// equals the FP64 sum of the face fluxes, Phi = C_{o,mask} . u_stencil, with
+// the flux coefficients C = w^T [S | N...] (w = reference mass-matrix row
+// sums).  Atab (FP32): [16 classes][10 steps][64 lanes] float; (BF16):
+// [16 classes][2 steps][hi, mid][64 lanes][8] bf16; Ctab: [16][40] double;
 // Wtab: [2][16] double (row weights, zero beyond 10); inv_wsum = 1 / sum w.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// two FP32 values rounded to nearest-even BF16, packed (a in the low half)
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+
+// BF16 hi/lo operands of five values x[0..4] (slots 5..7 zero): x_hi is x
+// rounded to BF16 and x_lo the rounded remainder x - x_hi, which FP32 holds
+// exactly.
+__device__ __forceinline__ void split_bf16x5(const float (&x)[5], bf16x8_t* hi, bf16x8_t* lo) {
+  const uint32_t h01 = pack_bf16(x[0], x[1]), h23 = pack_bf16(x[2], x[3]),
+                 h4 = pack_bf16(x[4], 0.f);
+  const float r0 = x[0] - __uint_as_float(h01 << 16);
+  const float r1 = x[1] - __uint_as_float(h01 & 0xffff0000u);
+  const float r2 = x[2] - __uint_as_float(h23 << 16);
+  const float r3 = x[3] - __uint_as_float(h23 & 0xffff0000u);
+  const float r4 = x[4] - __uint_as_float(h4 << 16);
+  typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+  const u32x4_t vh = {h01, h23, h4, 0u};
+  const u32x4_t vl = {pack_bf16(r0, r1), pack_bf16(r2, r3), pack_bf16(r4, 0.f), 0u};
+  *hi = __builtin_bit_cast(bf16x8_t, vh);
+  *lo = __builtin_bit_cast(bf16x8_t, vl);
+}
+
+template <bool BF>
 __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__ us, const float* ub,
                                                        float* out, const int4* __restrict__ elem,
-                                                       int64_t E, const float* __restrict__ Atab,
+                                                       int64_t E, const void* __restrict__ Atab,
                                                        const double* __restrict__ Ctab,
                                                        const double* __restrict__ Wtab,
                                                        double inv_wsum, int mode, double cb,
@@ -614,24 +657,35 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
       const int mask = (m.w >> 1) & 7;
       const int cls = o * 8 + mask;
       const uint32_t self = (uint32_t)e * 10u * (uint32_t)R;
-      // every load first: pivot row, the ten operand rows (stencil rows
-      // 4 s + q, the host guarantees E * 10 * R < 2^31), the own rows this
-      // lane writes (u and base), the class's operator entries
+      // every load first: pivot row, the ten operand rows of this lane (the
+      // host guarantees E * 10 * R < 2^31), the own rows this lane writes
+      // (u and base), the class's operator entries
       f32x4 cpv = *(const f32x4*)(us + self + col);
       f32x4 v[10];
-      float a[10];
       double cf[10];
 #pragma unroll
       for (int s = 0; s < 10; ++s) {
-        const int k = 4 * s + q;
+        const int k = BF ? 20 * (s / 5) + 5 * q + s % 5 : 4 * s + q;
         const int blk = k / 10, j = k % 10;
         int eb = (int)e;
         if (blk == 1 && m.x >= 0) eb = m.x;
         if (blk == 2 && m.y >= 0) eb = m.y;
         if (blk == 3 && m.z >= 0) eb = m.z;
         v[s] = *(const f32x4*)(us + ((uint32_t)eb * 10u + (uint32_t)j) * (uint32_t)R + col);
-        a[s] = Atab[(cls * 10 + s) * WAVE + lane];
         cf[s] = Ctab[cls * 40 + k];
+      }
+      float a[10];
+      bf16x8_t ahi[2], amid[2];
+      if constexpr (BF) {
+        const bf16x8_t* At = (const bf16x8_t*)Atab;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          ahi[h] = At[((cls * 2 + h) * 2 + 0) * WAVE + lane];
+          amid[h] = At[((cls * 2 + h) * 2 + 1) * WAVE + lane];
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 10; ++s) a[s] = ((const float*)Atab)[(cls * 10 + s) * WAVE + lane];
       }
       f32x4 u0[4], b0[4];
 #pragma unroll
@@ -652,10 +706,26 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
       for (int t = 0; t < 4; ++t) {
         f32x4 d = {0.f, 0.f, 0.f, 0.f};
         double phi = 0.0;
+        if constexpr (BF) {
 #pragma unroll
-        for (int s = 0; s < 10; ++s) {
-          d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], v[s][t] - cpv[t], d, 0, 0, 0);
-          phi = fma(cf[s], (double)v[s][t], phi);
+          for (int h = 0; h < 2; ++h) {
+            float x[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) x[j] = v[5 * h + j][t] - cpv[t];
+            bf16x8_t xh, xl;
+            split_bf16x5(x, &xh, &xl);
+            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(amid[h], xh, d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[h], xl, d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[h], xh, d, 0, 0, 0);
+          }
+#pragma unroll
+          for (int s = 0; s < 10; ++s) phi = fma(cf[s], (double)v[s][t], phi);
+        } else {
+#pragma unroll
+          for (int s = 0; s < 10; ++s) {
+            d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], v[s][t] - cpv[t], d, 0, 0, 0);
+            phi = fma(cf[s], (double)v[s][t], phi);
+          }
         }
         double dl = phi;
 #pragma unroll
@@ -1388,14 +1458,19 @@ void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub
 #undef DGD_PACKED_LAUNCH1
 }
 
-void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4* elem, int64_t E,
-                          const float* Atab, const double* Ctab, const double* Wtab, double wsum,
-                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st,
-                          const uint32_t* step, int stage_id) {
+void launch_stage_p3_mfma(bool bf16x3, const void* us, const void* ub, void* out,
+                          const int4* elem, int64_t E, const void* Atab, const double* Ctab,
+                          const double* Wtab, double wsum, int mode, double cb, double cg, int R,
+                          const Shape& sh, hipStream_t st, const uint32_t* step, int stage_id) {
   const dim3 grid((unsigned)sh.grid, (unsigned)((R + WAVE - 1) / WAVE));
-  hipLaunchKernelGGL(k_stage_p3_mfma, grid, dim3(64 * sh.waves), 0, st, (const float*)us,
-                     (const float*)ub, (float*)out, elem, E, Atab, Ctab, Wtab, 1.0 / wsum, mode, cb,
-                     cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0, step, stage_id);
+  if (bf16x3)
+    hipLaunchKernelGGL(k_stage_p3_mfma<true>, grid, dim3(64 * sh.waves), 0, st, (const float*)us,
+                       (const float*)ub, (float*)out, elem, E, Atab, Ctab, Wtab, 1.0 / wsum, mode,
+                       cb, cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0, step, stage_id);
+  else
+    hipLaunchKernelGGL(k_stage_p3_mfma<false>, grid, dim3(64 * sh.waves), 0, st, (const float*)us,
+                       (const float*)ub, (float*)out, elem, E, Atab, Ctab, Wtab, 1.0 / wsum, mode,
+                       cb, cg, R, sh.epw, sh.blocks, sh.remap ? 1 : 0, step, stage_id);
 }
 
 void launch_cheb(int np, const double* tcur, const double* tprev, double* tnext, double* res,

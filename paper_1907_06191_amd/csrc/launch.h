@@ -49,10 +49,13 @@ void launch_stage_packed(int prec, int np, int G, const void* us, const void* ub
 // P3 stage on matrix cores (FP32 state, R % 16 == 0; each wave walks epw
 // elements for 64 right-hand sides, grid.y covers the rest), same modes and
 // coefficients as launch_stage, with a per-element FP64 mass correction.
-void launch_stage_p3_mfma(const void* us, const void* ub, void* out, const int4* elem, int64_t E,
-                          const float* Atab, const double* Ctab, const double* Wtab, double wsum,
-                          int mode, double cb, double cg, int R, const Shape& sh, hipStream_t st,
-                          const uint32_t* step = nullptr, int stage_id = 0);
+// bf16x3: BF16 hi/lo split products (Atab in the BF16 lane order), else FP32
+// products (Atab in the FP32 lane order).
+void launch_stage_p3_mfma(bool bf16x3, const void* us, const void* ub, void* out,
+                          const int4* elem, int64_t E, const void* Atab, const double* Ctab,
+                          const double* Wtab, double wsum, int mode, double cb, double cg, int R,
+                          const Shape& sh, hipStream_t st, const uint32_t* step = nullptr,
+                          int stage_id = 0);
 
 // One step of the Chebyshev recurrence for exp(t L) (FP64 state):
 //   tnext = 2 (tcur + cg L(tcur)) - tprev,   res += ck * tnext.

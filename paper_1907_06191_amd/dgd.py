@@ -352,7 +352,7 @@ def dgd_run_set_step_count(run, steps: int) -> None:
     _check(_lib.dgd_run_set_step_count(run, int(steps)))
 
 
-KERNEL_NAMES = ("valu", "packed", "mfma")
+KERNEL_NAMES = ("valu", "packed", "mfma", "mfma_bf16x3")
 
 
 def dgd_run_kernel(run):

@@ -128,6 +128,21 @@ def test_argument_errors_without_device():
     with pytest.raises(dgd.DGDError) as e:
         dgd.dgd_operator_build(m.handle, 2, -2.0, 10.0, dgd.DGD_FP64, 1e-3)
     assert e.value.code == dgd.DGD_EINVAL
+    # the BF16 hi/lo split is the P3 primal operator with zero-flux walls
+    # only; an unknown precision is refused
+    for p in (1, 2):
+        with pytest.raises(dgd.DGDError) as e:
+            dgd.dgd_operator_build(m.handle, p, 2.0, 10.0, dgd.DGD_BF16X3, 1e-3)
+        assert e.value.code == dgd.DGD_EINVAL
+    with pytest.raises(dgd.DGDError) as e:
+        dgd.dgd_operator_build_outer(m.handle, 3, 2.0, 10.0, dgd.DGD_BF16X3, 1e-3, dgd.DGD_OUTER_ABSORB)
+    assert e.value.code == dgd.DGD_EINVAL
+    with pytest.raises(dgd.DGDError) as e:
+        dgd.dgd_operator_build_mixed(m.handle, np.zeros((0, 3)), 3, 2.0, dgd.DGD_BF16X3, 1e-3)
+    assert e.value.code == dgd.DGD_EINVAL
+    with pytest.raises(dgd.DGDError) as e:
+        dgd.dgd_operator_build(m.handle, 3, 2.0, 10.0, 3, 1e-3)
+    assert e.value.code == dgd.DGD_EINVAL
 
 
 def test_tuning_table_text_round_trip():

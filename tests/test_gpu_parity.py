@@ -401,6 +401,102 @@ def test_p3_mfma_solve_matches_valu_and_oracle(dgd):
     assert drift < 2.5e-6
 
 
+def _bf16x3_case(dgd):
+    disks = np.array([[1.5, 2.5, 0.6], [4.2, 4.4, 0.7], [5.6, 0.4, 0.5]])
+    L, N, D = 6.0, 6, 1.7
+    mesh = dgd.Mesh(L, N, disks)
+    op = dgd.Operator(mesh, 3, D, 10.0, dgd.DGD_BF16X3, dt_max_ms=1e-3)
+    assert op.info()[2] == dgd.DGD_BF16X3
+    m = omesh.build_mesh(L, N, disks)
+    oo = sipg.assemble(m, 3, D, 10.0)
+    npn, nodes, _ = op.info()
+    ci, cj, ori = mesh.elements()
+    key = {(int(a), int(b), int(c)): e for e, (a, b, c) in enumerate(zip(m.cell_i, m.cell_j, m.orient))}
+    perm = np.array([key[(int(a), int(b), int(c))] for a, b, c in zip(ci, cj, ori)])
+    T = _nodal_transform(oo, nodes)
+    n = m.n_elements * npn
+    Tb = np.zeros((n, n))
+    for e in range(m.n_elements):
+        Tb[e * npn:(e + 1) * npn, perm[e] * npn:(perm[e] + 1) * npn] = T[int(ori[e])]
+    Lref = Tb @ oo.L.toarray() @ np.linalg.inv(Tb)
+    return mesh, op, Lref, n
+
+
+def test_bf16x3_operator_extraction_and_apply(dgd):
+    """The P3 BF16 hi/lo split stage (DGD_BF16X3) against the oracle's
+    -M^-1 A.  Unit vectors split exactly (0, +-1 are BF16 values), so the
+    extracted operator carries only the operator's own split (A_hi + A_mid,
+    16 significant bits, the dropped remainder below 2^-18 of each entry,
+    at most doubled by the mass correction): 1.5e-5 of max |L|.  On random state in [-1, 1] the state split adds its
+    error (below 2^-17 of each |u - c|): every output within 2^-13 of
+    sum_k |L_ik| (the row's scale, with |u - c| <= 2), against FP32-product
+    errors of 2^-22."""
+    import torch
+    say("P3 BF16X3 operator extraction")
+    mesh, op, Lref, n = _bf16x3_case(dgd)
+    R = (n + 15) // 16 * 16
+    x = torch.zeros((n, R), dtype=torch.float32, device="cuda")
+    x[:, :n] = torch.eye(n, dtype=torch.float32, device="cuda")
+    y = torch.zeros_like(x)
+    op.apply(x, y, R)
+    torch.cuda.synchronize()
+    Lg = y[:, :n].double().cpu().numpy()
+    err = np.abs(Lg - Lref).max() / np.abs(Lref).max()
+    say(f"  max |L_bf16x3 - L_oracle| / max|L| = {err:.2e}")
+    assert err < 1.5e-5
+    # random state, 32 columns
+    rng = np.random.default_rng(5)
+    xr = rng.uniform(-1.0, 1.0, size=(n, 32))
+    xt = torch.tensor(xr, dtype=torch.float32, device="cuda")
+    yt = torch.zeros_like(xt)
+    op.apply(xt, yt, 32)
+    torch.cuda.synchronize()
+    yref = Lref @ xt.double().cpu().numpy()
+    scale = np.abs(Lref) @ np.full((n, 1), 2.0)
+    rel = (np.abs(yt.double().cpu().numpy() - yref) / scale).max()
+    say(f"  random state: max |y - y_ref| / (|L| 2) = {rel:.2e} (bound {2.0 ** -13:.2e})")
+    assert rel < 2.0 ** -13
+    # the split needs blocks of 16 right-hand sides
+    with pytest.raises(dgd.DGDError) as e:
+        op.apply(xt, yt, 24)
+    assert e.value.code == dgd.DGD_EINVAL
+
+
+def test_bf16x3_solve_matches_oracle(dgd):
+    """P3 RK3 with BF16 hi/lo split products (DGD_BF16X3) on a dense
+    packing, 16 start points: Sigma within 1e-4 of the oracle and of the
+    FP32 vector path; the FP64 mass correction keeps M0 to the stochastic
+    rounding walk of the FP32 state (2.5e-6, as for the FP32 products)."""
+    g, pts = _small_dense_case(nrhs=16, N=32, seed=21)
+    deltas = [0.05, 0.1]
+    prob = osolve.prepare(g.L, g.N, g.disks, 3, 2.0, 10.0)
+    dt = prob.dt["dt_nom"]
+    say(f"P3 BF16X3 solve: {prob.op.mesh.n_elements} elements, dt={dt:.3e}")
+    ref = osolve.solve(prob, pts, 0.3, deltas, method="cheb")
+    mesh = dgd.Mesh(g.L, g.N, g.disks)
+    op = dgd.Operator(mesh, 3, 2.0, 10.0, dgd.DGD_BF16X3, dt_max_ms=dt)
+    run = dgd.Run(op, pts, 0.3)
+    assert dgd.dgd_run_kernel(run.handle)[0] == "mfma_bf16x3"
+    run.close()
+    sig_b, mom_b = op.solve(pts, 0.3, deltas)
+    op32 = dgd.Operator(mesh, 3, 2.0, 10.0, dgd.DGD_FP32, dt_max_ms=dt)
+    dgd.dgd_set_option("p3_mfma", 0)
+    try:
+        sig_v, _ = op32.solve(pts, 0.3, deltas)
+    finally:
+        dgd.dgd_set_option("p3_mfma", 2)
+    e_ref = omom.rel_err(sig_b, omom.sigma_a(ref)).max()
+    e_valu = omom.rel_err(sig_b, sig_v).max()
+    drift = np.abs(mom_b[..., 0] - 1).max()
+    say(f"  bf16x3 vs oracle {e_ref:.2e}, vs fp32 valu {e_valu:.2e}, |M0-1| {drift:.2e}")
+    assert e_ref < 1e-4 and e_valu < 1e-4
+    assert drift < 2.5e-6
+    # 8 start points are not a multiple of 16: refused
+    with pytest.raises(dgd.DGDError) as e:
+        op.solve(pts[:8], 0.3, deltas)
+    assert e.value.code == dgd.DGD_EINVAL
+
+
 @pytest.mark.parametrize("p", [1, 2, 3])
 def test_expm_solve_matches_oracle_flow(dgd, p):
     """Chebyshev exponential on the GPU (FP64 state) against the oracle's
