@@ -198,7 +198,7 @@ def plain(args):
               "packed": f"k_stage_packed<{ts},{npn},{4 if R <= 16 else 2}>",
               "valu": f"k_stage<{ts},{npn}>"}[kind]
     dtype = {"mfma": "f32 MFMA contraction + f64 mass correction, f32 state",
-             "mfma_bf16x3": "bf16 hi/lo split MFMA contraction (3 products, f32 accumulate) "
+             "mfma_bf16x3": "bf16 hi/lo split MFMA contraction (4 products, f32 accumulate) "
                             "+ f64 mass correction, f32 state"}.get(
         kind, "f64 arithmetic, f32 state" if sbytes == 4 else "f64")
     out = base_record(args, value, ms_per_step, dtype, {
@@ -224,17 +224,18 @@ def plain(args):
         # the method's flops per element and right-hand side: the 10 x 10
         # self block and one 10 x 10 block per present face (2 Np^2 (1 + faces));
         # interior faces count twice, once from each side.  The BF16 split
-        # does the contraction three times (A_mid x_hi, A_hi x_lo, A_hi x_hi).
+        # does the contraction four times (A_lo x_hi, A_mid x_hi, A_hi x_lo,
+        # A_hi x_hi).
         method = 2.0 * npn * npn * (info["n_active"] + 2 * info["n_faces"]) * R
-        nprod = 3 if kind == "mfma_bf16x3" else 1
+        nprod = 4 if kind == "mfma_bf16x3" else 1
         peak = 2500.0 if kind == "mfma_bf16x3" else 157.3
-        issued = (2 * 3 * 16 * 16 * 32 * 2 if nprod == 3 else 10 * 16 * 16 * 4 * 2) * info["n_active"] * R / 16
+        issued = (2 * 4 * 16 * 16 * 32 * 2 if nprod == 4 else 10 * 16 * 16 * 4 * 2) * info["n_active"] * R / 16
         rate = method * nprod / (launch_ms * 1e-3) / 1e12
         out["roofline_mfma"] = {
             "bound": "mfma", "achieved": round(rate, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(rate / peak, 5), "flops_per_launch": method * nprod,
             "issued_flops_per_launch": issued,
-            "dtype": ("bf16 MFMA (v_mfma_f32_16x16x32_bf16), 3 split products" if nprod == 3 else
+            "dtype": ("bf16 MFMA (v_mfma_f32_16x16x32_bf16), 4 split products" if nprod == 4 else
                       "fp32 MFMA (v_mfma_f32_16x16x4_f32)"),
             "note": "method flops 2 Np^2 (1 + present faces) per element and right-hand side, "
                     "times the products the split needs; issued counts the padded 16 x 16 tiles"}

@@ -114,8 +114,9 @@ void dgd_mesh_destroy(dgd_mesh* mesh);
  *     timed them faster than the FP64 vector kernel), or DGD_BF16X3 (p = 3,
  *     zero-flux walls: FP32 state, every RK3 stage contracts the stacked
  *     element stencil on matrix cores as BF16 hi/lo split products --
- *     operator in two BF16 terms, state differences in two, three products
- *     accumulated in FP32, error below about 2^-16 of each product -- with
+ *     operator in three BF16 terms, state differences in two, four
+ *     products accumulated in FP32, error below about 2^-16 of each
+ *     product, from the state's split only -- with
  *     the FP64 per-element mass correction (section 3.1 remark on p <= 3);
  *     runs need a multiple of 16 right-hand sides (EINVAL otherwise), the
  *     Chebyshev exponential runs its FP64 vector path, and batches refuse

@@ -401,15 +401,16 @@ static double bf16_value(uint16_t b) {
 // rows 10..15 zero), in FP32 and in the lane order of v_mfma_f32_16x16x4
 // (lane l, step s holds A[l % 16][4 s + l / 16], stored [class][s][lane]); C = w^T A in FP64 with
 // w the row sums of the reference mass matrix; W = w padded to 16.  With
-// DGD_BF16X3 also A = A_hi + A_mid in BF16 (A_hi = A rounded, A_mid = the
-// remainder rounded) in the lane order of v_mfma_f32_16x16x32_bf16 as the
-// kernel uses it: lane l, step h, slot j < 5 holds A[l % 16][20 h + 5 (l / 16) + j],
-// slots 5..7 zero, stored [class][h][hi, mid][lane][slot].
+// DGD_BF16X3 also A = A_hi + A_mid + A_lo in BF16 (each term the rounded
+// remainder of the ones before) in the lane order of v_mfma_f32_16x16x32_bf16
+// as the kernel uses it: lane l, step h, slot j < 5 holds
+// A[l % 16][20 h + 5 (l / 16) + j], slots 5..7 zero, stored
+// [class][h][hi, mid, lo][lane][slot].
 void build_p3_tables(dgd_op* op) {
   const RefElem& R = op->ref;
   const int np = R.np;  // 10
   std::vector<float> At(16 * 64 * 10, 0.f);
-  std::vector<uint16_t> Ab(op->bf16x3 ? 16 * 2 * 2 * 64 * 8 : 0, 0);
+  std::vector<uint16_t> Ab(op->bf16x3 ? 16 * 2 * 3 * 64 * 8 : 0, 0);
   std::vector<double> Ct(16 * 40, 0.0), Wt(2 * 16, 0.0);
   double wsum = 0;
   for (int o = 0; o < 2; ++o) {
@@ -441,11 +442,12 @@ void build_p3_tables(dgd_op* op) {
       for (int h = 0; h < 2; ++h)
         for (int l = 0; l < 64; ++l)
           for (int j = 0; j < 5; ++j) {
-            const double a = A[(l % 16) * 40 + 20 * h + 5 * (l / 16) + j];
-            const uint16_t hi = bf16_rne(a);
-            const uint16_t mid = bf16_rne(a - bf16_value(hi));
-            Ab[((((size_t)cls * 2 + h) * 2 + 0) * 64 + l) * 8 + j] = hi;
-            Ab[((((size_t)cls * 2 + h) * 2 + 1) * 64 + l) * 8 + j] = mid;
+            double rest = A[(l % 16) * 40 + 20 * h + 5 * (l / 16) + j];
+            for (int term = 0; term < 3; ++term) {
+              const uint16_t b = bf16_rne(rest);
+              Ab[((((size_t)cls * 2 + h) * 3 + term) * 64 + l) * 8 + j] = b;
+              rest -= bf16_value(b);
+            }
           }
     }
   }

@@ -134,10 +134,10 @@ struct dgd_op {
   // P3 matrix-core path (FP32 state): A operands in lane order, FP64 flux
   // coefficients and mass-row weights (see the MFMA stage kernel)
   float* d_Atab = nullptr;   // [16][10][64]
-  // DGD_BF16X3: the same operands split into BF16 hi + mid, and every P3
-  // stage on the split-product kernel
+  // DGD_BF16X3: the same operands split into BF16 hi + mid + lo, and every
+  // P3 stage on the split-product kernel
   bool bf16x3 = false;
-  uint16_t* d_Atab_bf = nullptr;  // [16][2][2][64][8]
+  uint16_t* d_Atab_bf = nullptr;  // [16][2][3][64][8]
   double* d_Ctab = nullptr;  // [16][40]
   double* d_Wtab = nullptr;  // [2][16]
   double wsum = 0;
@@ -166,7 +166,7 @@ struct RunTarget {
   const int* blk_start = nullptr;// device [G + 1] reduction-block range of each geometry (G > 1)
   int64_t nblk_red = 0;          // reduction blocks covering the elements
   const float* Atab = nullptr;   // P3 matrix-core tables (NULL: VALU path only)
-  const uint16_t* Atab_bf = nullptr;  // BF16 hi/mid tables; non-NULL: every stage on them
+  const uint16_t* Atab_bf = nullptr;  // BF16 hi/mid/lo tables; non-NULL: every stage on them
   const double* Ctab = nullptr;
   const double* Wtab = nullptr;
   double wsum = 0;

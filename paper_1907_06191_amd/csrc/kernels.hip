@@ -574,12 +574,19 @@ __global__ void __launch_bounds__(256) k_mixed_div(const TS* __restrict__ q, con
 //    slot j < 5 of stencil row k = 20 h + 5 (l / 16) + j and slots 5..7 zero,
 //    for row m = l % 16 of A and column n = l % 16 of B (the operand layout
 //    only has to give a lane's slot j the same k in A and in B, which the
-//    instruction does).  A is split on the host into A_hi + A_mid, both BF16
-//    (16 significant bits together); each value x = u - c is split here into
-//    x_hi = bf16(x) and x_lo = bf16(x - x_hi) (error below 2^-17 |x|), and
-//    the step accumulates A_mid x_hi + A_hi x_lo + A_hi x_hi in FP32 (the
-//    dropped A_mid x_lo is below 2^-18).  Six matrix instructions per block
-//    of 16 right-hand sides instead of ten at twice the cost each.
+//    instruction does).  A is split on the host into A_hi + A_mid + A_lo,
+//    all BF16 (24 significant bits together); each value x = u - c is split
+//    here into x_hi = bf16(x) and x_lo = bf16(x - x_hi) (error below
+//    2^-17 |x|), and the step accumulates
+//    A_lo x_hi + A_mid x_hi + A_hi x_lo + A_hi x_hi in FP32.  What is left
+//    out (A_mid x_lo, A_lo x_lo, the rounding of x_lo) depends on the
+//    rounding residues of the state, which vary from element to element;
+//    the operator's own remainder would not: a fixed relative error e in
+//    the stencil breaks its consistency on linear fields, a source of
+//    relative size e l / h on a field varying over a length l, so A keeps
+//    its third term (with two, e = 2^-18 moved Sigma by ~5e-5).  Eight
+//    matrix instructions per block of 16 right-hand sides instead of ten
+//    at twice the cost each.
 // Either way lane l receives D[m = 4 (l / 16) + i][n = l % 16], i < 4.
 //
 // A wave covers 64 right-hand sides of an element (blockIdx.y selects which
@@ -596,7 +603,7 @@ __global__ void __launch_bounds__(256) k_mixed_div(const TS* __restrict__ q, con
 // equals the FP64 sum of the face fluxes, Phi = C_{o,mask} . u_stencil, with
 // the flux coefficients C = w^T [S | N...] (w = reference mass-matrix row
 // sums).  Atab (FP32): [16 classes][10 steps][64 lanes] float; (BF16):
-// [16 classes][2 steps][hi, mid][64 lanes][8] bf16; Ctab: [16][40] double;
+// [16 classes][2 steps][hi, mid, lo][64 lanes][8] bf16; Ctab: [16][40] double;
 // Wtab: [2][16] double (row weights, zero beyond 10); inv_wsum = 1 / sum w.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
@@ -627,7 +634,7 @@ __device__ __forceinline__ void split_bf16x5(const float (&x)[5], bf16x8_t* hi, 
 }
 
 template <bool BF>
-__global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__ us, const float* ub,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_stage_p3_mfma(const float* __restrict__ us, const float* ub,
                                                        float* out, const int4* __restrict__ elem,
                                                        int64_t E, const void* __restrict__ Atab,
                                                        const double* __restrict__ Ctab,
@@ -675,52 +682,75 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
         cf[s] = Ctab[cls * 40 + k];
       }
       float a[10];
-      bf16x8_t ahi[2], amid[2];
-      if constexpr (BF) {
-        const bf16x8_t* At = (const bf16x8_t*)Atab;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          ahi[h] = At[((cls * 2 + h) * 2 + 0) * WAVE + lane];
-          amid[h] = At[((cls * 2 + h) * 2 + 1) * WAVE + lane];
-        }
-      } else {
+      if constexpr (!BF) {
 #pragma unroll
         for (int s = 0; s < 10; ++s) a[s] = ((const float*)Atab)[(cls * 10 + s) * WAVE + lane];
       }
-      f32x4 u0[4], b0[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = 4 * q + i;
-        const uint32_t idx = self + (uint32_t)(row < 10 ? row : 0) * (uint32_t)R + col;
-        if (mode != 0) {
-          u0[i] = *(const f32x4*)(us + idx);
-          b0[i] = use_base ? *(const f32x4*)(ub + idx) : u0[i];
-        }
+      // After the products lane (q, n) holds rows 4q .. 4q+3 of its four
+      // columns: 16 values, of which 16, 16, 8 and 0 are real rows (< 10)
+      // for q = 0..3.  The combine and rounding are rebalanced to ten values
+      // per lane, three row pieces each: lanes q = 3 take rows 3 and 7 and
+      // row 2's last two columns, lanes q = 2 row 6's last two columns
+      // (cross-lane moves by 32 and 48 lanes; n is kept):
+      //   q   piece A (4 cols)  piece B (4 cols)  piece C (2 cols from tC)
+      //   0   row 0             row 1             row 2, tC = 0
+      //   1   row 4             row 5             row 6, tC = 0
+      //   2   row 8             row 9             row 6, tC = 2
+      //   3   row 3             row 7             row 2, tC = 2
+      const int rA = q == 3 ? 3 : 4 * q, rB = q == 3 ? 7 : 4 * q + 1;
+      const int rC = (q == 0 || q == 3) ? 2 : 6, tC = q < 2 ? 0 : 2;
+      const uint32_t iA = self + (uint32_t)rA * (uint32_t)R + col;
+      const uint32_t iB = self + (uint32_t)rB * (uint32_t)R + col;
+      const uint32_t iC = self + (uint32_t)rC * (uint32_t)R + col + (uint32_t)tC;
+      f32x4 uA, uB, bA, bB;
+      f32x2_t uC, bC;
+      if (mode != 0) {
+        uA = *(const f32x4*)(us + iA);
+        uB = *(const f32x4*)(us + iB);
+        uC = *(const f32x2_t*)(us + iC);
+        bA = use_base ? *(const f32x4*)(ub + iA) : uA;
+        bB = use_base ? *(const f32x4*)(ub + iB) : uB;
+        bC = use_base ? *(const f32x2_t*)(ub + iC) : uC;
       }
       double wr[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) wr[i] = Wtab[o * 16 + 4 * q + i];
       f32x4 acc[4];
       double alpha[4];
+      if constexpr (BF) {
+        // step h outermost, so only one step's three operator terms are live
+        const bf16x8_t* At = (const bf16x8_t*)Atab;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        f32x4 d = {0.f, 0.f, 0.f, 0.f};
-        double phi = 0.0;
-        if constexpr (BF) {
+        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < 2; ++h) {
+          const bf16x8_t ahi = At[((cls * 2 + h) * 3 + 0) * WAVE + lane];
+          const bf16x8_t amid = At[((cls * 2 + h) * 3 + 1) * WAVE + lane];
+          const bf16x8_t alo = At[((cls * 2 + h) * 3 + 2) * WAVE + lane];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
             float x[5];
 #pragma unroll
             for (int j = 0; j < 5; ++j) x[j] = v[5 * h + j][t] - cpv[t];
             bf16x8_t xh, xl;
             split_bf16x5(x, &xh, &xl);
-            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(amid[h], xh, d, 0, 0, 0);
-            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[h], xl, d, 0, 0, 0);
-            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[h], xh, d, 0, 0, 0);
+            f32x4 d = acc[t];
+            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, xh, d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(amid, xh, d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, xl, d, 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, xh, d, 0, 0, 0);
           }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        double phi = 0.0;
+        f32x4 d = acc[t];
+        if constexpr (BF) {
 #pragma unroll
           for (int s = 0; s < 10; ++s) phi = fma(cf[s], (double)v[s][t], phi);
         } else {
+          d = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int s = 0; s < 10; ++s) {
             d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], v[s][t] - cpv[t], d, 0, 0, 0);
@@ -735,26 +765,50 @@ __global__ void __launch_bounds__(256) k_stage_p3_mfma(const float* __restrict__
         acc[t] = d;
         alpha[t] = dl * inv_wsum;
       }
-      if (!col_live) continue;
+      // the moves (every lane takes part; only q = 2, 3 keep what arrives)
+      f32x4 vA, vB;
+      f32x2_t vC;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = 4 * q + i;
-        if (row >= 10) continue;
-        const uint32_t idx = self + (uint32_t)row * (uint32_t)R + col;
-        f32x4 r4;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const double val = (double)acc[t][i] + alpha[t];
-          if (mode == 0) {
-            r4[t] = (float)(cg * val);
-          } else {
-            const double uu = (double)u0[i][t], bb = (double)b0[i][t];
-            r4[t] = round_stochastic(bb + cb * (uu - bb) + cg * val,
-                                     sr_node(state_salt(m.w, (int)col + t, smix), row));
-          }
-        }
-        *(f32x4*)(out + idx) = r4;
+      for (int t = 0; t < 4; ++t) {
+        const float m48 = __shfl_xor(acc[t][3], 48), m32 = __shfl_xor(acc[t][3], 32);
+        vA[t] = q == 3 ? m48 : acc[t][0];
+        vB[t] = q == 3 ? m32 : acc[t][1];
       }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const float m48 = __shfl_xor(acc[2 + k][2], 48);
+        vC[k] = q < 2 ? acc[k][2] : m48;
+      }
+      if (!col_live) continue;
+      auto finish = [&](float a_val, int t, int row, float uu, float bb) -> float {
+        const double val = (double)a_val + alpha[t];
+        if (mode == 0) return (float)(cg * val);
+        const double u = (double)uu, b0 = (double)bb;
+        return round_stochastic(b0 + cb * (u - b0) + cg * val,
+                                sr_node(state_salt(m.w, (int)col + t, smix), row));
+      };
+      f32x4 oA, oB;
+      f32x2_t oC;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        oA[t] = finish(vA[t], t, rA, mode != 0 ? uA[t] : 0.f, mode != 0 ? bA[t] : 0.f);
+        oB[t] = finish(vB[t], t, rB, mode != 0 ? uB[t] : 0.f, mode != 0 ? bB[t] : 0.f);
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const double al = tC == 0 ? alpha[k] : alpha[2 + k];
+        const double val = (double)vC[k] + al;
+        if (mode == 0) {
+          oC[k] = (float)(cg * val);
+        } else {
+          const double u = (double)uC[k], b0 = (double)bC[k];
+          oC[k] = round_stochastic(b0 + cb * (u - b0) + cg * val,
+                                   sr_node(state_salt(m.w, (int)col + tC + k, smix), rC));
+        }
+      }
+      *(f32x4*)(out + iA) = oA;
+      *(f32x4*)(out + iB) = oB;
+      *(f32x2_t*)(out + iC) = oC;
     }
   }
 }

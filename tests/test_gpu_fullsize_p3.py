@@ -6,6 +6,8 @@ points, all 20 Delta).
 * Chebyshev exponential (FP64 state): every Delta to 30 ms, 1e-8 on Sigma.
 * RK3 on matrix cores (FP32 state, forced): the first Delta (about 150k
   steps), 1e-4 on Sigma.
+* RK3 with BF16 hi/lo split products (DGD_BF16X3): the first two Delta,
+  1e-4 on Sigma (all 20 Delta, about 4.7 million steps, with DGD_LONG=1).
 """
 
 import json
@@ -108,3 +110,47 @@ def test_fullsize_p3_rk3_valu_first_delta(case):
     assert err.max() < 1e-4
     assert drift < 1e-5
     op.close()
+
+
+def _bf16x3_deltas(case, nd):
+    dgd, c, gold, mesh, pts, idx = case
+    sel = np.sort(np.concatenate([idx, idx + 1]))
+    pos = np.searchsorted(sel, idx)
+    op = dgd.Operator(mesh, 3, c["D"], c["eta"], dgd.DGD_BF16X3, dt_max_ms=gold["dt_nom"])
+    run = dgd.Run(op, pts[sel], c["sigma0"])
+    assert dgd.dgd_run_kernel(run.handle)[0] == "mfma_bf16x3"
+    dt, prev, mom = gold["dt_nom"], 0.0, []
+    ref = np.asarray(gold["moments"])
+    for k, d in enumerate(gold["deltas"][:nd]):
+        n = int(np.ceil((d - prev) / dt - 1e-9))
+        run.advance(n, (d - prev) / n)
+        mom.append(run.moments())
+        prev = d
+        e = omom.rel_err(omom.sigma_a(mom[-1][pos][:, None]), omom.sigma_a(ref[:, k:k + 1])).max()
+        say(f"  Delta {d:.3f} ms ({n} steps): rel err {e:.2e}, |M0-1| {np.abs(mom[-1][:, 0] - 1).max():.1e}")
+    run.close()
+    mom = np.stack(mom, axis=1)
+    err = omom.rel_err(omom.sigma_a(mom[pos]), omom.sigma_a(ref[:, :nd]))
+    drift = np.abs(mom[..., 0] - 1).max()
+    say(f"  max rel err vs oracle {err.max():.2e}; |M0-1| {drift:.2e}")
+    op.close()
+    return err, drift
+
+
+def test_fullsize_p3_rk3_bf16x3_first_deltas(case):
+    """DGD_BF16X3 (every stage on matrix cores as BF16 hi/lo split products)
+    over the first two Delta on the 8 stored start points and the 8
+    following ones (16 right-hand sides)."""
+    say("full-size P3 RK3, BF16 hi/lo split products, first two Delta")
+    err, drift = _bf16x3_deltas(case, 2)
+    assert err.max() < 1e-4
+    assert drift < 1e-5
+
+
+@pytest.mark.skipif(os.environ.get("DGD_LONG") != "1",
+                    reason="about 15 minutes of GPU time: run with DGD_LONG=1")
+def test_fullsize_p3_rk3_bf16x3_all_deltas(case):
+    say("full-size P3 RK3, BF16 hi/lo split products, all Delta to 30 ms")
+    err, drift = _bf16x3_deltas(case, 20)
+    assert err.max() < 1e-4
+    assert drift < 1e-5
