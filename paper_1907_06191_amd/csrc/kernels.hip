@@ -376,6 +376,10 @@ __global__ void __launch_bounds__(256) k_mixed_grad(const TS* __restrict__ us, T
   const int r_raw = blockIdx.y * WAVE + lane;
   const bool live = r_raw < R;
   const int r = live ? r_raw : R - 1;
+  // state rows through buffer resources, as in k_stage
+  const uint32_t voff = (uint32_t)r * (uint32_t)sizeof(TS);
+  const uint32_t row = (uint32_t)R * (uint32_t)sizeof(TS);
+  const int64_t elen = (int64_t)NP * R;
   const BlockIter it = block_iter(nblocks, remap);
   for (int64_t b = it.first; b < it.end; b += it.stride) {
     const int64_t e0 = (b * (blockDim.x / WAVE) + w) * (int64_t)epw;
@@ -386,27 +390,29 @@ __global__ void __launch_bounds__(256) k_mixed_grad(const TS* __restrict__ us, T
       const int4 m = elem[e];
       const int o = m.w & 1;
       const int mask = (m.w >> 1) & 7;
-      const int64_t self = (e * NP) * (int64_t)R + r;
-      const int64_t n0 = (m.x >= 0 ? (int64_t)m.x * NP * R + r : self);
-      const int64_t n1 = (m.y >= 0 ? (int64_t)m.y * NP * R + r : self);
-      const int64_t n2 = (m.z >= 0 ? (int64_t)m.z * NP * R + r : self);
+      const TS* pe = us + e * elen;
+      const __amdgpu_buffer_rsrc_t ru = rows_at(pe);
+      const __amdgpu_buffer_rsrc_t r0 = rows_at(m.x >= 0 ? us + (int64_t)m.x * elen : pe);
+      const __amdgpu_buffer_rsrc_t r1 = rows_at(m.y >= 0 ? us + (int64_t)m.y * elen : pe);
+      const __amdgpu_buffer_rsrc_t r2 = rows_at(m.z >= 0 ? us + (int64_t)m.z * elen : pe);
       // a neighbour enters only through its nodes on the shared face
       const int* c0 = MNcol + (o * 3 + 0) * NF;
       const int* c1 = MNcol + (o * 3 + 1) * NF;
       const int* c2 = MNcol + (o * 3 + 2) * NF;
       TS su[NP], s0[NF], s1[NF], s2[NF];
 #pragma unroll
-      for (int j = 0; j < NP; ++j) su[j] = us[self + (int64_t)j * R];
+      for (int j = 0; j < NP; ++j) su[j] = ld_row<TS>(ru, voff, j * row);
 #pragma unroll
       for (int k = 0; k < NF; ++k) {
-        s0[k] = us[n0 + (int64_t)c0[k] * R];
-        s1[k] = us[n1 + (int64_t)c1[k] * R];
-        s2[k] = us[n2 + (int64_t)c2[k] * R];
+        s0[k] = ld_row<TS>(r0, voff, (uint32_t)c0[k] * row);
+        s1[k] = ld_row<TS>(r1, voff, (uint32_t)c1[k] * row);
+        s2[k] = ld_row<TS>(r2, voff, (uint32_t)c2[k] * row);
       }
       const double c = (double)su[0];
       double d[NP];
+      d[0] = 0.0;
 #pragma unroll
-      for (int j = 0; j < NP; ++j) d[j] = (double)su[j] - c;
+      for (int j = 1; j < NP; ++j) d[j] = (double)su[j] - c;
       double ax[NP], ay[NP];
       {
         const double* Gx = MG + ((o * 8 + mask) * 2 + 0) * NP * NP;
@@ -415,7 +421,7 @@ __global__ void __launch_bounds__(256) k_mixed_grad(const TS* __restrict__ us, T
         for (int i = 0; i < NP; ++i) {
           double a = 0.0, bb = 0.0;
 #pragma unroll
-          for (int j = 0; j < NP; ++j) {
+          for (int j = 1; j < NP; ++j) {
             a = fma(Gx[i * NP + j], d[j], a);
             bb = fma(Gy[i * NP + j], d[j], bb);
           }
@@ -444,11 +450,11 @@ __global__ void __launch_bounds__(256) k_mixed_grad(const TS* __restrict__ us, T
       DGD_MFACE(2, s2)
 #undef DGD_MFACE
       if (!live) continue;
-      const int64_t qb = (e * 2 * NP) * (int64_t)R + r;
+      const __amdgpu_buffer_rsrc_t rq = rows_at(qout + 2 * e * elen);
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
-        qout[qb + (int64_t)i * R] = (TS)ax[i];
-        qout[qb + (int64_t)(NP + i) * R] = (TS)ay[i];
+        st_row<DGD_CPOL_OUT>(rq, voff, i * row, (TS)ax[i]);
+        st_row<DGD_CPOL_OUT>(rq, voff, (NP + i) * row, (TS)ay[i]);
       }
     }
   }
@@ -471,6 +477,9 @@ __global__ void __launch_bounds__(256) k_mixed_div(const TS* __restrict__ q, con
   const int r_raw = blockIdx.y * WAVE + lane;
   const bool live = r_raw < R;
   const int r = live ? r_raw : R - 1;
+  const uint32_t voff = (uint32_t)r * (uint32_t)sizeof(TS);
+  const uint32_t row = (uint32_t)R * (uint32_t)sizeof(TS);
+  const int64_t elen = (int64_t)NP * R;
   const bool use_base = ub != nullptr;
   const uint32_t smix = step_mix(step, stage_id);
   const BlockIter it = block_iter(nblocks, remap);
@@ -483,78 +492,93 @@ __global__ void __launch_bounds__(256) k_mixed_div(const TS* __restrict__ q, con
       const int mt = meta[e];
       const int fm = mt & 7;
       const bool ext = (mt >> 3) & 1;
-      const int64_t self = (e * NP) * (int64_t)R + r;
+      const __amdgpu_buffer_rsrc_t ro = rows_at(out + e * elen);
       // axon element: u stays zero (k = 0, no q-flux); only the operator
       // apply (mode 0) writes its zero derivative
       if (!ext) {
         if (mode == 0 && live) {
 #pragma unroll
-          for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)0;
+          for (int i = 0; i < NP; ++i) st_row(ro, voff, i * row, (TS)0);
         }
         continue;
       }
-      double acc[NP];
+      // every load first: own q, the neighbours' q on the shared faces,
+      // the stage input and the RK base
+      const __amdgpu_buffer_rsrc_t rq = rows_at(q + 2 * e * elen);
+      TS qx[NP], qy[NP], su[NP], sb[NP];
 #pragma unroll
-      for (int i = 0; i < NP; ++i) acc[i] = 0.0;
-      if (ext) {
-        const int64_t qs = (e * 2 * NP) * (int64_t)R + r;
-        double qx[NP], qy[NP];
+      for (int j = 0; j < NP; ++j) {
+        qx[j] = ld_row<TS>(rq, voff, j * row);
+        qy[j] = ld_row<TS>(rq, voff, (NP + j) * row);
+      }
+      TS fx[3][NF], fy[3][NF];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) {
-          qx[j] = (double)q[qs + (int64_t)j * R];
-          qy[j] = (double)q[qs + (int64_t)(NP + j) * R];
+      for (int f = 0; f < 3; ++f) {
+        const int nb = f == 0 ? m.x : (f == 1 ? m.y : m.z);
+        // a face off the q-flux reads the element's own rows (unused)
+        const __amdgpu_buffer_rsrc_t rn = rows_at(((fm >> f) & 1) ? q + 2 * (int64_t)nb * elen
+                                                                   : q + 2 * e * elen);
+        const int* cf = MNcol + (o * 3 + f) * NF;
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+          fx[f][k] = ld_row<TS>(rn, voff, (uint32_t)cf[k] * row);
+          fy[f][k] = ld_row<TS>(rn, voff, (uint32_t)(NP + cf[k]) * row);
         }
+      }
+      if (mode != 0) {
+        const __amdgpu_buffer_rsrc_t ru = rows_at(us + e * elen);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) su[j] = ld_row<TS>(ru, voff, j * row);
+        if (use_base) {
+          const __amdgpu_buffer_rsrc_t rb = rows_at(ub + e * elen);
+#pragma unroll
+          for (int j = 0; j < NP; ++j) sb[j] = ld_row<TS, DGD_CPOL_BASE>(rb, voff, j * row);
+        }
+      }
+      double acc[NP];
+      {
         const double* Dx = MD + ((o * 8 + fm) * 2 + 0) * NP * NP;
         const double* Dy = MD + ((o * 8 + fm) * 2 + 1) * NP * NP;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
           double a = 0.0;
 #pragma unroll
-          for (int j = 0; j < NP; ++j) a = fma(Dx[i * NP + j], qx[j], fma(Dy[i * NP + j], qy[j], a));
+          for (int j = 0; j < NP; ++j)
+            a = fma(Dx[i * NP + j], (double)qx[j], fma(Dy[i * NP + j], (double)qy[j], a));
           acc[i] = a;
         }
+      }
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
-          if (!((fm >> f) & 1)) continue;
-          const int nb = f == 0 ? m.x : (f == 1 ? m.y : m.z);
-          const int64_t qn = ((int64_t)nb * 2 * NP) * R + r;
-          const int* cf = MNcol + (o * 3 + f) * NF;
-          double fx[NF], fy[NF];
+      for (int f = 0; f < 3; ++f) {
+        if (!((fm >> f) & 1)) continue;
+        const double* Nx = MN + ((o * 3 + f) * 2 + 0) * NP * NF;
+        const double* Ny = MN + ((o * 3 + f) * 2 + 1) * NP * NF;
 #pragma unroll
-          for (int k = 0; k < NF; ++k) {
-            fx[k] = (double)q[qn + (int64_t)cf[k] * R];
-            fy[k] = (double)q[qn + (int64_t)(NP + cf[k]) * R];
-          }
-          const double* Nx = MN + ((o * 3 + f) * 2 + 0) * NP * NF;
-          const double* Ny = MN + ((o * 3 + f) * 2 + 1) * NP * NF;
+        for (int i = 0; i < NP; ++i) {
+          double a = acc[i];
 #pragma unroll
-          for (int i = 0; i < NP; ++i) {
-            double a = acc[i];
-#pragma unroll
-            for (int k = 0; k < NF; ++k) a = fma(Nx[i * NF + k], fx[k], fma(Ny[i * NF + k], fy[k], a));
-            acc[i] = a;
-          }
+          for (int k = 0; k < NF; ++k)
+            a = fma(Nx[i * NF + k], (double)fx[f][k], fma(Ny[i * NF + k], (double)fy[f][k], a));
+          acc[i] = a;
         }
       }
       if (!live) continue;
       const uint32_t hsr = state_salt(m.w, r, smix);
       if (mode == 0) {
 #pragma unroll
-        for (int i = 0; i < NP; ++i) out[self + (int64_t)i * R] = (TS)(cg * acc[i]);
+        for (int i = 0; i < NP; ++i) st_row(ro, voff, i * row, (TS)(cg * acc[i]));
       } else if (use_base) {
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-          const double u = (double)us[self + (int64_t)i * R];
-          const double b0 = (double)ub[self + (int64_t)i * R];
-          store_state(out, self + (int64_t)i * R, b0 + cb * (u - b0) + cg * acc[i],
-                      hsr, i);
+          const double u = (double)su[i], b0 = (double)sb[i];
+          st_row<DGD_CPOL_OUT>(ro, voff, i * row,
+                               to_state((TS*)nullptr, b0 + cb * (u - b0) + cg * acc[i], hsr, i));
         }
       } else {
 #pragma unroll
-        for (int i = 0; i < NP; ++i) {
-          const double u = (double)us[self + (int64_t)i * R];
-          store_state(out, self + (int64_t)i * R, u + cg * acc[i], hsr, i);
-        }
+        for (int i = 0; i < NP; ++i)
+          st_row<DGD_CPOL_OUT>(ro, voff, i * row,
+                               to_state((TS*)nullptr, (double)su[i] + cg * acc[i], hsr, i));
       }
     }
   }
