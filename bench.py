@@ -19,8 +19,9 @@ Also reported:
     Delta list, moments) with the Chebyshev exponential integrator
     (--no-expm skips it);
   * --workload batch256-p12: the batched solve (256 uneven geometries, P1/P2
-    groups, 16 start points each); --workload pack256-p3: P3 on matrix cores, 128 start
-    points.
+    groups, 16 start points each); --workload pack256-p3: P3, 128 start
+    points (FP64 vector kernel, or with --precision bf16x3 BF16 hi/lo split
+    products on matrix cores).
 
 Prints one JSON line.
 """
@@ -47,9 +48,10 @@ HBM_PEAK_GBS = 8000.0
 # per wave, waves, XCD order, workgroups): a changed kernel source or
 # another tuned shape reports traffic null.  Summaries: profiles/.
 MEASURED_TRAFFIC = {
-    ("pack512-p2", "k_stage<float,6>", "16abf2790a26ceac", (2, 4, 0, 26674)): 1129.6e6,
-    ("pack512-p2", "k_stage<float,3>", "16abf2790a26ceac", (2, 4, 0, 26674)): 566.5e6,
-    ("pack256-p3", "k_stage<float,10>", "16abf2790a26ceac", (2, 1, 1, 23936)): 660.3e6,
+    ("pack512-p2", "k_stage<float,6>", "e201530676e6d977", (2, 4, 0, 26674)): 1129.6e6,
+    ("pack512-p2", "k_stage<float,3>", "e201530676e6d977", (2, 4, 0, 26674)): 566.5e6,
+    ("pack256-p3", "k_stage<float,10>", "e201530676e6d977", (2, 1, 1, 23936)): 660.3e6,
+    ("pack256-p3", "k_stage_p3_mfma<true>", "e201530676e6d977", (4, 1, 1, 11968)): 752.9e6,
 }
 
 
