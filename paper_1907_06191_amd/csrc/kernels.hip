@@ -207,9 +207,11 @@ __device__ __forceinline__ double to_state(double*, double v, uint32_t, int) { r
 // of the base state (BASE) and of absorbing box blocks (ABS) is fixed too;
 // without it both are tested at run time.  Which instantiation is faster
 // depends on the register allocation: P3 gains from SPLIT, P1 and P2 lose
-// (measured on gfx950), so the launcher splits for np = 10 only.
+// (measured on gfx950), so the launcher splits for np = 10 only.  P3 with
+// an FP32 state is held to 96 VGPRs (five waves per SIMD instead of four;
+// no spills).
 template <typename TS, int NP, int MODE, bool SPLIT, bool BASE, bool ABS>
-__global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const TS* ub, TS* out,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NP == 10 && sizeof(TS) == 4 ? 5 : 1))) k_stage(const TS* __restrict__ us, const TS* ub, TS* out,
                                                const int4* __restrict__ elem, int64_t E,
                                                const double* __restrict__ S,
                                                const double* __restrict__ Nm, int mode, double cb,
@@ -362,6 +364,8 @@ __global__ void __launch_bounds__(256) k_stage(const TS* __restrict__ us, const 
 // fm: faces whose both sides are extracellular (the harmonic mean of k is
 // zero otherwise).  meta[e] = fm | extracellular << 3.  The stage combine and
 // the stochastic rounding of FP32 stores are those of k_stage (modes 0, 1).
+// The P3 FP32 divergence pass is held to 128 VGPRs (four waves per SIMD
+// instead of three; no spills).
 template <typename TS, int NP>
 __global__ void __launch_bounds__(256) k_mixed_grad(const TS* __restrict__ us, TS* __restrict__ qout,
                                                     const int4* __restrict__ elem,
@@ -461,7 +465,8 @@ __global__ void __launch_bounds__(256) k_mixed_grad(const TS* __restrict__ us, T
 }
 
 template <typename TS, int NP>
-__global__ void __launch_bounds__(256) k_mixed_div(const TS* __restrict__ q, const TS* __restrict__ us,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(TS) == 4 && NP == 10 ? 4 : 1)))
+k_mixed_div(const TS* __restrict__ q, const TS* __restrict__ us,
                                                    const TS* ub, TS* out,
                                                    const int4* __restrict__ elem,
                                                    const uint8_t* __restrict__ meta, int64_t E,
