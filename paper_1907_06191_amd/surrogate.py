@@ -128,7 +128,7 @@ def rel_err(a, b):
 
 
 def evaluate(s, images, targets, halves, deltas, dg_seconds, thresholds):
-    """Surrogate against the DG judge on held-out geometries: error of the
+    """Surrogate against the DG solve on held-out geometries: error of the
     ensemble mean, the 16-point target's sampling noise (half the distance
     between the two 8-point halves), and per spread threshold the fallback
     rate, the error of the accepted answers and the gain in queries per

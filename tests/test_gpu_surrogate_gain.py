@@ -1,12 +1,12 @@
-"""What the trained surrogate gains over the DG solve alone, judged by the
-DG solve, on geometries it never saw.
+"""What the trained surrogate gains over the DG solve alone, measured against
+the DG solve, on geometries it never saw.
 
 The shipped ensemble (paper_1907_06191_amd/surrogate_weights.npz: 4
 members trained by `python -m paper_1907_06191_amd.surrogate` on 1,250
 seeded geometries x 20 Delta, augmented 4x by the mesh's exact symmetries)
 predicts Sigma / (2 D Delta) for 64 held-out geometries (numbers 1250..1313
 of the surrogate recipe) at the 20 Delta in [1, 50] ms.  The batched DG solve
-of the same geometries and start points gives the judge's answer, the
+of the same geometries and start points gives the reference answer, the
 16-start-point target's sampling noise (half the distance between the two
 8-point means) and the time of answering every query with DG.
 
@@ -55,7 +55,7 @@ def test_surrogate_gain_on_held_out_geometries():
     say(f"surrogate gain: {len(members)} members, held-out geometries {ids.start}..{ids.stop - 1}")
     geos = sur.geometries(ids, workers=8)
     deltas = sur.deltas_default()
-    images, targets, halves, t_dg = sur.dg_targets(geos, deltas, label="DG judge")
+    images, targets, halves, t_dg = sur.dg_targets(geos, deltas, label="DG reference")
     rep, mean, spread = sur.evaluate(s, images, targets, halves, deltas, t_dg, sur.THRESHOLDS)
     say(json.dumps(rep))
     by = {b["threshold"]: b for b in rep["by_threshold"]}
