@@ -11,7 +11,7 @@ Element weak forms (eq. (7)) with the fluxes of section 3.2:
 {a} = (a- + a+)/2 (central flux for u), k_h = 2 k- k+ / (k- + k+) (the
 harmonic mean, 0 when either side is an axon cell: no flow between axon
 and extracellular cells).  On the square's edges (zero flux, the default
-outer condition of this build): the u-flux is u- itself and the q-flux is
+outer condition of the library): the u-flux is u- itself and the q-flux is
 zero.  With the gradient of the trial function moved back,
 
   q = grad_h u + sum_F lift_F((u+ - u-)/2),

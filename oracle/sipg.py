@@ -2,7 +2,7 @@
 
 The paper writes diffusion as the first-order system q = grad u,
 u_t = div(k q) (eq. (6)), with element weak forms (eq. (7)), a central flux
-for u and a harmonic-mean flux for q (section 3.2).  This build uses the
+for u and a harmonic-mean flux for q (section 3.2).  The main path uses the
 primal symmetric interior-penalty form instead, on the extracellular
 triangles only (removed axon cells, zero flux on their faces):
 
