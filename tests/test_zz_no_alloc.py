@@ -1,6 +1,7 @@
 """The allocation-free solve (dgd_eap_solve_noalloc) against dgd_eap_solve.
 
-Both entry points run the same kernels on the same data; the allocation-free
+Both entry points run the same kernels on the same data (P2 FP64, P1 FP32
+and P3 with BF16 hi/lo split products); the allocation-free
 one keeps its buffers in the library's fixed device scratch, launches its
 steps eagerly and uses the option's launch shape unless a tuned one exists.
 The stage kernels give the same bits for every launch shape, so the two
@@ -40,6 +41,9 @@ CASES = [
     (7.5, 24, 3, 2, "fp64", 2, [0.01, 0.025]),
     (10.0, 32, 5, 1, "fp32", 16, [0.02, 0.05]),
     (7.5, 24, 3, 1, "fp32", 3, [0.02, 0.05]),
+    # P3 with BF16 hi/lo split products on matrix cores (multiples of 16 points)
+    (10.0, 32, 5, 3, "bf16x3", 32, [0.005, 0.01]),
+    (7.5, 24, 3, 3, "bf16x3", 16, [0.005, 0.01]),
 ]
 
 
@@ -49,7 +53,7 @@ def test_noalloc_matches_solve(dgd):
         g = make_geometry(L, N, 19070619 + 40 + k, n_disks=nd)
         pts = start_points(g.disks, g.L, g.N, R, np.random.default_rng(19070619 + 50 + k))
         mesh = dgd.Mesh(g.L, g.N, g.disks)
-        pr = dgd.DGD_FP64 if prec == "fp64" else dgd.DGD_FP32
+        pr = {"fp64": dgd.DGD_FP64, "fp32": dgd.DGD_FP32, "bf16x3": dgd.DGD_BF16X3}[prec]
         op = dgd.Operator(mesh, p, 2.0, 10.0, pr)
         sig_a, mom_a = dgd.dgd_eap_solve(op.handle, pts, 0.3, deltas)
         sig_b, mom_b = dgd.dgd_eap_solve_noalloc(op.handle, pts, 0.3, deltas)
