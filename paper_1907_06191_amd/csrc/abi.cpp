@@ -857,6 +857,9 @@ hipGraphExec_t step_graph(dgd_run* run, int64_t n, double dt) {
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) fail(DGD_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   run->graphs[key] = ex;
+  // upload now, so that the first replay (which may fall in a caller's timed
+  // region) costs what later ones do
+  DGD_HIP_CHECK(hipGraphUpload(ex, run->stream));
   return ex;
 }
 
