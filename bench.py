@@ -242,6 +242,8 @@ def plain(args):
             "note": "method flops 2 Np^2 (1 + present faces) per element and right-hand side, "
                     "times the products the split needs; issued counts the padded 16 x 16 tiles"}
     run.close()
+    if args.full_solve:
+        out["full_solve"] = full_solve_leg(args, dgd, op, pts, c, dt, ws, stream, p)
     if args.expm:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -271,6 +273,52 @@ def plain(args):
         out["cpu_baseline"] = cpu_baseline(g, pts, p, c["D"], c["eta"], c["sigma0"], dt, lam,
                                            args.cpu_budget)
     return out
+
+
+def full_solve_leg(args, dgd, op, pts, c, dt, ws, stream, p):
+    """The whole RK3 solve timed end to end: projection of the 64 pulses,
+    every step of the Delta-landing schedule (each interval in ceil(span /
+    dt) equal steps), the moments at every Delta.  Sigma about the start
+    point (M2 / M0) is compared at the sampled start points with the values
+    the oracle stored in tests/golden (its exact semi-discrete flow)."""
+    import torch
+    golden = os.path.join(ROOT, "tests", "golden", f"{args.workload}_oracle.json")
+    gold = None
+    if os.path.exists(golden) and p == c["p"]:
+        with open(golden) as f:
+            gold = json.load(f)
+    R = pts.shape[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run = dgd.Run(op, pts, c["sigma0"], workspace=ws, stream=stream)
+    prev, total, mom = 0.0, 0, []
+    for d in c["deltas"]:
+        n = max(int(np.ceil((d - prev) / dt - 1e-9)), 1)
+        for a in range(0, n, 100000):
+            run.advance(min(100000, n - a), (d - prev) / n)
+            stream.synchronize()
+            log(f"full solve: Delta {d:.4f} ms, {min(a + 100000, n)} / {n} steps, "
+                f"{time.perf_counter() - t0:.0f} s")
+        mom.append(run.moments(check=False))
+        total += n
+        prev = d
+    el = time.perf_counter() - t0
+    run.close()
+    mom = np.stack(mom, axis=1)                   # [R][n_delta][6]
+    res = {"sigma_solves_per_s": round(R / el, 6), "seconds": round(el, 2), "steps": total,
+           "max_mass_drift": float(np.abs(mom[..., 0] - 1).max()),
+           "note": "measured end to end: projection, every RK3 step of the Delta list, "
+                   "moments at each Delta"}
+    if gold is not None:
+        idx = np.asarray(gold["sample_index"])
+        ref = np.asarray(gold["moments"])
+        s = mom[idx][..., 3:6] / mom[idx][..., 0:1]
+        r = ref[..., 3:6] / ref[..., 0:1]
+        fro = lambda v: np.sqrt(v[..., 0] ** 2 + 2.0 * v[..., 1] ** 2 + v[..., 2] ** 2)
+        res["max_rel_err_sigma_vs_oracle"] = float((fro(s - r) / fro(r)).max())
+        res["oracle_sample"] = (f"{len(idx)} of the {R} start points, all {len(c['deltas'])} Delta "
+                                f"(tests/golden/{args.workload}_oracle.json)")
+    return res
 
 
 def mixed_leg(args, dgd, g, pts, p, c, prec, R, primal_sigma_per_s, n_ext):
@@ -374,6 +422,9 @@ def main():
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-expm", dest="expm", action="store_false")
+    ap.add_argument("--full-solve", action="store_true",
+                    help="also run the whole RK3 solve (every step of the Delta list) timed end to "
+                         "end, checked at the sampled start points against the stored oracle values")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
                     help="skip the mixed-form leg (the paper's own formulation on all pixels)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
