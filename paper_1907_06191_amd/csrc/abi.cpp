@@ -381,21 +381,6 @@ void build_mixed_tables(dgd_op* op, const double* disks, int n_disks) {
   op->form = 1;
 }
 
-// FP32 and BF16 round to nearest even (finite values)
-static uint16_t bf16_rne(double x) {
-  const float f = (float)x;
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-static double bf16_value(uint16_t b) {
-  const uint32_t u = (uint32_t)b << 16;
-  float f;
-  std::memcpy(&f, &u, 4);
-  return f;
-}
-
 // Tables of the P3 matrix-core kernel: for class (o, mask) the stacked
 // stencil matrix A = [S | N_0 | N_1 | N_2] (10 x 40, missing faces zero,
 // rows 10..15 zero), in FP32 and in the lane order of v_mfma_f32_16x16x4
@@ -442,12 +427,10 @@ void build_p3_tables(dgd_op* op) {
       for (int h = 0; h < 2; ++h)
         for (int l = 0; l < 64; ++l)
           for (int j = 0; j < 5; ++j) {
-            double rest = A[(l % 16) * 40 + 20 * h + 5 * (l / 16) + j];
-            for (int term = 0; term < 3; ++term) {
-              const uint16_t b = bf16_rne(rest);
-              Ab[((((size_t)cls * 2 + h) * 3 + term) * 64 + l) * 8 + j] = b;
-              rest -= bf16_value(b);
-            }
+            uint16_t t[3];
+            split_bf16x3(A[(l % 16) * 40 + 20 * h + 5 * (l / 16) + j], t);
+            for (int term = 0; term < 3; ++term)
+              Ab[((((size_t)cls * 2 + h) * 3 + term) * 64 + l) * 8 + j] = t[term];
           }
     }
   }

@@ -79,6 +79,11 @@ RefElem build_ref_elem(int p, double eta);
 // cell's lower-left corner) of the orientation-o triangle.
 void eval_nodal_basis(const RefElem& R, int o, double x, double y, double* out);
 std::vector<double> build_ic_quadrature(const RefElem& R, int n);
+// An operator entry as three BF16 terms t[0] + t[1] + t[2] (bit patterns),
+// each the remainder of the ones before rounded to nearest even (through
+// FP32): together 24 significant bits, |a - sum| below about 2^-26 |a|.
+void split_bf16x3(double a, uint16_t t[3]);
+double bf16_value(uint16_t b);
 // Element order: cells ranked in vertical strips of `strip` columns (each
 // strip row by row; strip <= 0: plain rows); the ranked cells are taken in
 // runs of `group` cells, each run giving the T0 of its cells, then their T1.

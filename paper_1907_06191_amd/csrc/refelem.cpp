@@ -22,6 +22,7 @@
 // Integrals use Gauss-Legendre rules (collapsed product rule on the
 // triangle), exact for the polynomial degrees involved.
 #include <cmath>
+#include <cstring>
 #include <stdexcept>
 
 #include "dgd_internal.h"
@@ -384,6 +385,25 @@ RefElem build_ref_elem(int p, double eta) {
     }
   }
   return R;
+}
+
+double bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+void split_bf16x3(double a, uint16_t t[3]) {
+  double rest = a;
+  for (int k = 0; k < 3; ++k) {
+    const float f = (float)rest;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    t[k] = (uint16_t)(u >> 16);
+    rest -= bf16_value(t[k]);
+  }
 }
 
 void eval_nodal_basis(const RefElem& R, int o, double x, double y, double* out) {

@@ -1,8 +1,9 @@
 // Host-code checker built with AddressSanitizer and UndefinedBehaviorSanitizer
 // (g++ -fsanitize=address,undefined, no device code): drives the library's
 // host-only parts -- the pixel mesh builder, the reference-element and
-// quadrature builder, and the launch-shape table parser -- over ordinary and
-// edge-case inputs, and checks their invariants.  Any out-of-bounds access,
+// quadrature builder, the BF16 split of operator entries, and the
+// launch-shape table parser -- over ordinary and edge-case inputs, and
+// checks their invariants.  Any out-of-bounds access,
 // use after free, leak or undefined operation aborts with the sanitizer's
 // report; a failed invariant exits with status 1.
 //
@@ -146,6 +147,35 @@ static void reference_elements() {
   }
 }
 
+// The BF16 three-term split of operator entries (matrix-core tables):
+// together within 2^-26 of the entry, terms shrinking by 2^-8 or more, a
+// value that is already BF16 kept whole, zero split into zeros.
+static void check_split(double a) {
+  uint16_t t[3];
+  split_bf16x3(a, t);
+  const double v0 = bf16_value(t[0]), v1 = bf16_value(t[1]), v2 = bf16_value(t[2]);
+  CHECK(std::fabs(a - (v0 + v1 + v2)) <= std::ldexp(std::fabs(a), -26));
+  CHECK(std::fabs(v1) <= std::ldexp(std::fabs(v0), -8) * (1.0 + 1e-6));
+  CHECK(std::fabs(v2) <= std::ldexp(std::fabs(v1), -8) * (1.0 + 1e-6));
+}
+
+static void bf16_split() {
+  std::mt19937_64 rng(1907);
+  std::uniform_real_distribution<double> U(-1.0, 1.0);
+  std::uniform_int_distribution<int> X(-40, 40);
+  for (int k = 0; k < 100000; ++k) check_split(std::ldexp(U(rng), X(rng)));
+  for (int p = 1; p <= 3; ++p) {
+    const RefElem R = build_ref_elem(p, 10.0);
+    for (double a : R.S) check_split(a);
+    for (double a : R.Nb) check_split(a);
+  }
+  for (double a : {1.0, -0.375, std::ldexp(3.0, -20), 0.0}) {
+    uint16_t t[3];
+    split_bf16x3(a, t);
+    CHECK(bf16_value(t[0]) == a && t[1] == 0 && t[2] == 0);
+  }
+}
+
 static void tune_table() {
   tune_clear();
   CHECK(tune_export().empty());
@@ -179,6 +209,7 @@ static void tune_table() {
 int main() {
   meshes();
   reference_elements();
+  bf16_split();
   tune_table();
   if (g_fail) return 1;
   std::printf("host checks passed\n");
