@@ -402,6 +402,15 @@ def batched(args):
         "workload": f"batch256-p12: batched solve, {n} geometries (grid edge 128..512 at h=100/512 um, "
                     f"phi 0.4..0.7), P1/P2 groups, {R} start points each",
         "groups": per_group})
+    # the dominant kernel: the group with the longest step
+    top = max(range(len(groups)), key=lambda k: per_group[k]["ms_per_step"])
+    npn = (groups[top]["p"] + 1) * (groups[top]["p"] + 2) // 2
+    kern = (f"k_stage_packed<float,{npn},{4 if R <= 16 else 2}>" if R <= 32 else f"k_stage<float,{npn}>")
+    out["roofline"] = dict(per_group[top]["roofline"], kernel=kern, traffic=None,
+                           group=f"P{groups[top]['p']}",
+                           traffic_note="HBM counters of this kernel on the batched workload: "
+                                        "profiles/k_stage_packed_batch256-p12.md (taken on an earlier "
+                                        "source with the same kernel body); null here")
     out["stage_shape_table"] = dgd.dgd_tune_export().strip().split("\n")
     out["sigma_solves_per_s"] = round(n * R / solve_s, 6)
     out["sigma_solves_note"] = "projected: measured ms/step per group x its full schedule"
