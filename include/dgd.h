@@ -438,7 +438,8 @@ void dgd_surrogate_destroy(dgd_surrogate* s);
  *                  (v_mfma_f32_16x16x4_f32, FP64 mass correction; the
  *                  right-hand-side count a multiple of 16): 0 = never,
  *                  1 = always, 2 (default) = when the autotuner timed them
- *                  faster than the VALU kernel for the run's key
+ *                  faster than the VALU kernel for the run's key (a
+ *                  DGD_BF16X3 operator always runs its split-product kernel)
  *   "mesh_strip"   element order of meshes created afterwards: vertical strips
  *                  of this many cell columns, each row-major (0 = plain rows)
  *   "mesh_group"   element order of meshes created afterwards: the ranked
