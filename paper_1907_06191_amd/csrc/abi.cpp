@@ -825,6 +825,10 @@ void run_stage_steps(dgd_run* run, int64_t n, double dt) {
   }
 }
 
+// Most step graphs a run keeps (a dt's set is at most 14: graph_steps and
+// the powers of two up to 4096).
+constexpr size_t kMaxRunGraphs = 128;
+
 hipGraphExec_t step_graph(dgd_run* run, int64_t n, double dt) {
   uint64_t bits;
   std::memcpy(&bits, &dt, sizeof(bits));
@@ -861,6 +865,17 @@ void run_advance(dgd_run* run, int64_t n_steps, double dt) {
     const int64_t G = g_opt.graph_steps;
     int64_t top = 1;
     while (2 * top <= G) top *= 2;
+    // The graphs are a cache: a run advanced with many different steps (one
+    // per Delta interval, or a caller's own schedule) drops them all, once
+    // its stream has drained, before the set of a new dt would pass
+    // kMaxRunGraphs.
+    uint64_t bits;
+    std::memcpy(&bits, &dt, sizeof(bits));
+    if (!run->graphs.count(std::make_pair(bits, G)) && run->graphs.size() + 14 > kMaxRunGraphs) {
+      DGD_HIP_CHECK(hipStreamSynchronize(run->stream));
+      for (auto& kv : run->graphs) (void)hipGraphExecDestroy(kv.second);
+      run->graphs.clear();
+    }
     std::vector<std::pair<int64_t, hipGraphExec_t>> ladder;
     ladder.emplace_back(G, step_graph(run, G, dt));
     for (int64_t s = top; s >= 1; s /= 2)

@@ -268,6 +268,35 @@ def test_determinism_graphs_and_checkpoint(dgd):
     r.close()
 
 
+def test_graph_cache_many_steps_sizes(dgd):
+    """A run advanced with 30 different steps (6 step graphs each, more than
+    the run keeps) drops and recaptures its graphs on the way and stays
+    bitwise equal to plain launches."""
+    g, pts = _small_dense_case(nrhs=4, N=32, seed=5)
+    prob = osolve.prepare(g.L, g.N, g.disks, 2, 2.0, 10.0)
+    dt = prob.dt["dt_nom"]
+    mesh = dgd.Mesh(g.L, g.N, g.disks)
+    op = dgd.Operator(mesh, 2, 2.0, 10.0, dgd.DGD_FP32, dt_max_ms=dt)
+    say("graph cache over 30 step sizes")
+
+    def run(graphs):
+        dgd.dgd_set_option("graphs", 1 if graphs else 0)
+        try:
+            r = dgd.Run(op, pts, 0.3)
+            for k in range(30):
+                r.advance(3 + k % 5, dt * (1.0 - 1e-3 * k))
+            m = r.moments()
+            r.close()
+        finally:
+            dgd.dgd_set_option("graphs", 1)
+        return m
+
+    a, b = run(True), run(False)
+    assert np.array_equal(a, b)
+    op.close()
+    mesh.close()
+
+
 def test_auto_dt_is_stable(dgd):
     """The library's own step rule (device power iteration) stays inside the
     RK3 stability interval for the oracle's largest eigenvalue."""
