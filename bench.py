@@ -48,10 +48,10 @@ HBM_PEAK_GBS = 8000.0
 # per wave, waves, XCD order, workgroups): a changed kernel source or
 # another tuned shape reports traffic null.  Summaries: profiles/.
 MEASURED_TRAFFIC = {
-    ("pack512-p2", "k_stage<float,6>", "38d481061b41ab9f", (2, 4, 0, 26674)): 1129.7e6,
-    ("pack512-p2", "k_stage<float,3>", "38d481061b41ab9f", (2, 4, 0, 26674)): 566.5e6,
-    ("pack256-p3", "k_stage<float,10>", "38d481061b41ab9f", (1, 1, 1, 47872)): 660.0e6,
-    ("pack256-p3", "k_stage_p3_mfma<true>", "38d481061b41ab9f", (4, 1, 1, 11968)): 752.4e6,
+    ("pack512-p2", "k_stage<float,6>", "b1461cb9119fe11a", (2, 4, 0, 26674)): 1129.6e6,
+    ("pack512-p2", "k_stage<float,3>", "b1461cb9119fe11a", (2, 4, 0, 26674)): 566.5e6,
+    ("pack256-p3", "k_stage<float,10>", "b1461cb9119fe11a", (1, 1, 1, 47872)): 660.0e6,
+    ("pack256-p3", "k_stage_p3_mfma<true>", "b1461cb9119fe11a", (4, 1, 1, 11968)): 752.7e6,
 }
 
 

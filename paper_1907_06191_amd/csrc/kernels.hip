@@ -202,7 +202,8 @@ __device__ __forceinline__ double to_state(double*, double v, uint32_t, int) { r
 // and the HBM traffic is that of the FP32 state.
 //
 // mode 2 (Chebyshev recurrence of exp(t L), see launch_cheb):
-//   out = 2 (us + cg L(us)) - ub,  res += ck * out.
+//   out = 2 (us + cg L(us)) - ub,  res += ck * out
+// (res loaded with the other loads; out and res stored non-temporally).
 // MODE is the runtime mode fixed at compile time.  With SPLIT the presence
 // of the base state (BASE) and of absorbing box blocks (ABS) is fixed too;
 // without it both are tested at run time.  Which instantiation is faster
@@ -263,6 +264,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NP == 
 #pragma unroll
         for (int j = 0; j < NP; ++j) sb[j] = ld_row<TS, DGD_CPOL_BASE>(rb, voff, j * row);
       }
+      TS sr[NP];
+      if constexpr (MODE == 2) {
+        const __amdgpu_buffer_rsrc_t rr = rows_at(res + e * elen);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) sr[j] = ld_row<TS, DGD_CPOL_BASE>(rr, voff, j * row);
+      }
       const double c = (double)su[0];
       double acc[NP];
       {
@@ -320,8 +327,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NP == 
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
           const double t = 2.0 * ((double)su[i] + cg * acc[i]) - (double)sb[i];
-          st_row(ro, voff, i * row, (TS)t);
-          st_row(rr, voff, i * row, (TS)((double)ld_row<TS>(rr, voff, i * row) + ck * t));
+          st_row<DGD_CPOL_OUT>(ro, voff, i * row, (TS)t);
+          st_row<DGD_CPOL_OUT>(rr, voff, i * row, (TS)((double)sr[i] + ck * t));
         }
       } else {
         const uint32_t hsr = elem_salt(m.w, smix) ^ hrhs;
